@@ -1,0 +1,77 @@
+"""Oracle geometry (Eqs. tangent, metric, covectors, gamma) pinned to closed
+forms (App. D polar basis; exact Cartesian cells) (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_01868_amd import grids as G
+
+
+@pytest.mark.parametrize("q", [9, 21])
+def test_polar_basis_matches_app_d(q):
+    Nr, Nt, M = 12, 48, 7.0
+    c = G.polar_annulus(q, Nr, Nt, M)
+    o = oracle.OracleGrid(c)
+    geo = o.geometry()
+    dth = 2 * math.pi / Nt
+    r = c.meta["centres"]
+    rr = np.repeat(r, Nt)
+    th = np.tile((np.arange(Nt) + 0.5) * dth, Nr)
+    rhat = np.stack([np.cos(th), np.sin(th)], 1)
+    that = np.stack([-np.sin(th), np.cos(th)], 1)
+    # App. D: g_1 = (r_{i+1} - r_{i-1}) / 2 r-hat, g_2 = r_i sin(dtheta) theta-hat
+    assert np.allclose(geo["g1"], 1.0 * rhat, atol=1e-13)
+    assert np.allclose(geo["g2"], (rr * math.sin(dth))[:, None] * that, atol=1e-13)
+    assert np.allclose(geo["J"], rr * math.sin(dth), rtol=1e-13)
+    assert np.allclose(geo["G"][:, 1], 0, atol=1e-13)
+    assert np.allclose(geo["G"][:, 0], 1.0, rtol=1e-13)
+    assert np.allclose(geo["G"][:, 2], 1.0 / (rr * math.sin(dth)) ** 2, rtol=1e-12)
+    # rotation equivariance: the Christoffel sums do not depend on the column
+    A = geo["Aplus"].reshape(Nr, Nt, q, 2)
+    assert np.abs(A - A[:, :1]).max() < 1e-12
+
+
+def test_cartesian_non_equilateral_cells_exact():
+    """dx = 2 dy cells: g_1 = (1,0), g_2 = (0,2), J = 2, g^ij = diag(1, 1/4), Theta = 0
+    exactly (binary coordinates)."""
+    c = G.workload_planar_couette_q9()
+    o = oracle.OracleGrid(c)
+    geo = o.geometry()
+    assert (geo["J"] == 2.0).all()
+    assert (geo["G"] == np.array([1.0, 0.0, 0.25])).all()
+    assert (geo["Aplus"] == 0).all() and (geo["Aminus"] == 0).all()
+
+
+def test_planar_stretched_theta():
+    """Linearly contracting channel: only Theta^1_1(p, q) = (h(p) - h(q)) / h(q) is nonzero."""
+    f = G.faces_linear(16, 0.4)
+    c = G.planar_channel(21, f, 3)
+    o = oracle.OracleGrid(c)
+    geo = o.geometry()
+    Xr = c.X[:, 0]
+    h = (Xr[2:] - Xr[:-2]) / 2.0        # g_1 length on rows -h+1 .. n1+h-2
+    H = c.halo
+    cl, *_ = oracle.lattice(21)
+    for i in range(16):
+        hq = h[i + H - 1]
+        for a in range(21):
+            c1 = cl[a][0]
+            ap = c1 * (h[i + H - 1 + c1] - hq) / hq
+            am = c1 * (h[i + H - 1 - c1] - hq) / hq
+            assert abs(geo["Aplus"][i * 3, a, 0] - ap) < 1e-13
+            assert abs(geo["Aminus"][i * 3, a, 0] - am) < 1e-13
+            assert abs(geo["Aplus"][i * 3, a, 1]) < 1e-15
+
+
+@pytest.mark.parametrize("q", [9, 21])
+def test_aminus_is_minus_aplus_of_opposite(q):
+    """A^-_alpha(q) = -A^+_{-alpha}(q): c^j_{-a} = -c^j_a in Eq. (gamma)."""
+    c = G.periodic_box(q, 10, 12, dx=1.0, dy=1.3, skew=0.2, wobble=0.4)
+    o = oracle.OracleGrid(c)
+    geo = o.geometry()
+    cl, *_ = oracle.lattice(q)
+    opp = [int(np.where((cl == -cl[a]).all(1))[0][0]) for a in range(q)]
+    assert np.allclose(geo["Aminus"], -geo["Aplus"][:, opp], atol=1e-14)
+    assert np.abs(geo["G"][:, 1]).max() > 0.01      # the skewed grid is non-orthogonal
