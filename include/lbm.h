@@ -1,0 +1,211 @@
+/*
+ * lbm.h -- C ABI of the MI355X volumetric curvilinear lattice Boltzmann library.
+ *
+ * The library advances the lattice Boltzmann equation of Chekhlov,
+ * Staroselsky, Zhang and Chen (arXiv:2301.01868, Sec. 2) on a body-fitted 2D
+ * grid: pull streaming in computational coordinates (Eq. adv), BGK collision
+ * toward the metric-dependent equilibrium (Eqs. collide, equilibrium), the
+ * inertial force from the discrete Christoffel symbols (Eqs. gamma,
+ * compo-constr), the momentum-flux correction (Eq. delta-flux) and the
+ * curvilinear correction (Eq. deltaN), with the periodic, no-slip and
+ * moving-wall boundaries of App. B and the "no flow" volume adjustment of
+ * Sec. 3.1.  D2Q9 and D2Q21 lattices (App. A).
+ *
+ * Conventions used by every entry point:
+ *   - q1 is the wall-normal computational index (rows i = 0..n1-1, walls at
+ *     i = -1/2 and n1 - 1/2), q2 the periodic index (columns j = 0..n2-1);
+ *   - all host arrays are row-major with q2 fastest; per-cell vectors are
+ *     cell-major ([cell][2]); population arrays are direction-major
+ *     ([alpha][i][j]); lengths are in lattice units (mean wall-normal step 1,
+ *     time step 1);
+ *   - velocities are contravariant components U^i in the tangent basis g_i;
+ *   - every call returns LBM_OK (0) or a negative LBM_E* code; the text of the
+ *     last error is lbm_last_error(grid) (or lbm_last_error(NULL) for errors
+ *     raised before a grid exists);
+ *   - host arrays passed in are owned by the caller and copied; output arrays
+ *     are allocated by the caller with the stated sizes;
+ *   - each grid is bound to one HIP stream; calls on one grid are not thread
+ *     safe; calls that return data to the host synchronise that stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* bad argument: shape, tau <= 1/2, J <= 0, halo too small, ... */
+    LBM_ENOMEM = -2,     /* device or host allocation failed */
+    LBM_EDEVICE = -3,    /* a HIP runtime call failed */
+    LBM_EUNSTABLE = -4,  /* a reduction found non-finite values or m <= 0 */
+    LBM_ESTATE = -5      /* call out of order (e.g. step before init) */
+};
+
+/* boundary kinds of the two q1 sides (App. B); q2 is always periodic */
+enum { LBM_PERIODIC = 0, LBM_NOSLIP = 1, LBM_MOVING = 2 };
+
+/* population storage / arithmetic */
+enum {
+    LBM_FP64 = 0,   /* FP64 populations, FP64 arithmetic */
+    LBM_FP32 = 1    /* FP32 populations stored as offsets from a per-cell base, FP32 arithmetic */
+};
+
+/* offset base for LBM_FP32 storage: the stored value is N_alpha - B_alpha */
+enum {
+    LBM_BASE_LOCAL_REST = 0, /* B = J rho0 f^eq_alpha(rho0, U = 0; g^ij) / rho0 (default) */
+    LBM_BASE_W_RHO0 = 1,     /* B = J w_alpha rho0 */
+    LBM_BASE_NONE = 2        /* B = 0 (always used for LBM_FP64) */
+};
+
+/* geometry table mode */
+enum {
+    LBM_GEOM_AUTO = 0,  /* per-row tables when the metric terms do not depend on q2 */
+    LBM_GEOM_CELL = 1   /* per-cell tables (general mappings) */
+};
+
+typedef struct lbm_grid lbm_grid;
+typedef struct lbm_batch lbm_batch;
+
+/* Device memory provider (e.g. PyTorch's caching allocator); NULL = hipMalloc. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} lbm_allocator;
+
+typedef struct {
+    int32_t q;              /* 9 or 21 */
+    int32_t n1, n2;         /* interior cells along q1 and q2 */
+    int32_t halo;           /* layers of the mapping given beyond the interior, >= c_max + 1 (2 or 4) */
+    const double *x, *y;    /* host: cell-centre coordinates on the halo-extended range,
+                               (n1 + 2 halo) x (n2 + 2 halo), q2 fastest; ghost rows beyond a wall
+                               hold the symmetrically continued geometry (Sec. 3.1) */
+    int32_t bc_lo, bc_hi;   /* q1 low / high side: LBM_NOSLIP, LBM_MOVING, or LBM_PERIODIC for both */
+    double ut_lo, ut_hi;    /* moving walls: contravariant tangential velocity U0^2 (App. B.3) */
+    double tau;             /* BGK relaxation time, > 1/2 */
+    double accel[2];        /* constant external acceleration, contravariant components */
+    double rho0;            /* reference density (initial state and offset base) */
+    int32_t precision;      /* LBM_FP64 | LBM_FP32 */
+    int32_t offset_base;    /* LBM_BASE_* (ignored for LBM_FP64) */
+    int32_t iterations;     /* 0: force with the lagged N'(q, t-1) (Sec. 2); k > 0: k extra
+                               fixed-point passes of the implicit force relation */
+    int32_t geometry;       /* LBM_GEOM_AUTO | LBM_GEOM_CELL */
+    const lbm_allocator *alloc; /* NULL: hipMalloc/hipFree */
+    void *stream;           /* hipStream_t for all work on this grid; NULL: the library makes one */
+} lbm_grid_desc;
+
+/* Residual and global diagnostics (all FP64, interior cells).  residual is
+ * |m Ut(t) - m Ut(t-K)|_2 / (K |m Ut(t)|_2) with K the steps since the last
+ * call (infinite on the first call); mass = sum m; kinetic_energy =
+ * sum m g_ij Ut^i Ut^j / 2; angular_momentum = sum m (x u_y - y u_x) with
+ * u = Ut^i g_i; bad_cells counts cells with non-finite values or m <= 0. */
+typedef struct {
+    int64_t step;
+    double residual;
+    double mass;
+    double mass_rel_drift;  /* relative to the mass at lbm_init */
+    double kinetic_energy;
+    double angular_momentum;
+    int64_t bad_cells;
+} lbm_resid;
+
+typedef struct {
+    int32_t q, n1, n2, pitch;
+    int32_t precision, row_tables; /* row_tables = 1 when per-row geometry tables are used */
+    int64_t step;
+    double bytes_per_update;       /* algorithmic HBM bytes per lattice update: 2 Q sizeof(population) */
+    size_t device_bytes;           /* device memory held by the grid */
+} lbm_grid_info;
+
+/* Lattice tables of App. A / App. B (host only): velocities cx[q], cy[q],
+ * weights w[q], T0.  Returns LBM_EINVAL for q other than 9 or 21. */
+int lbm_lattice(int32_t q, int32_t *cx, int32_t *cy, double *w, double *T0);
+
+/* Create a grid from a coordinate mapping (Sec. 2, Eqs. distance..gamma).
+ * Computes the geometry (tangent basis by central differences, metric,
+ * volume J, co-tangents, discrete Christoffel sums) in FP64 on the GPU, builds
+ * the step tables and allocates the double-buffered populations.  Errors:
+ * LBM_EINVAL (q, sizes, halo < c_max + 1, n1 < c_max with walls, tau <= 1/2,
+ * J <= 0 anywhere, unpaired periodic side), LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out);
+void lbm_grid_destroy(lbm_grid *g);
+const char *lbm_last_error(const lbm_grid *g);
+int lbm_grid_info_get(const lbm_grid *g, lbm_grid_info *out);
+
+/* Volume used for the initial state and the reported density: NULL restores
+ * the geometric J; otherwise J[n1*n2] > 0 (the "no flow" adjusted J', Sec. 3.1).
+ * The step itself does not depend on J (everything is in particle numbers). */
+int lbm_set_volume(lbm_grid *g, const double *J);
+
+/* Volume currently used for initial state and density output, J[n1*n2]. */
+int lbm_get_volume(lbm_grid *g, double *J);
+
+/* Initial state N = J f^eq(rho0, U = Ut = u0; g^ij), which also serves as the
+ * lagged N'(q, -1); u0[n1*n2][2] contravariant, or NULL for rest.  Resets the
+ * step counter and the residual reference. */
+int lbm_init(lbm_grid *g, const double *u0);
+
+/* Advance n time steps (asynchronous on the grid's stream). */
+int lbm_step(lbm_grid *g, int64_t n);
+
+/* Moments of the current state, computed as the next step would see them
+ * (pull, moments, force): m[n1*n2] = sum_alpha N_alpha (= J rho), U and Ut
+ * [n1*n2][2] contravariant; any pointer may be NULL.  Synchronises. */
+int lbm_moments(lbm_grid *g, double *m, double *U, double *Ut);
+
+/* FP64 residual and diagnostics (see lbm_resid).  Synchronises.  Returns
+ * LBM_EUNSTABLE (after filling *out) when bad_cells > 0. */
+int lbm_residual(lbm_grid *g, lbm_resid *out);
+
+/* The "no flow" adjustment of Sec. 3.1: from rest, with the grid's boundary
+ * kinds but zero wall velocities and zero external force, run to
+ * residual < tol (checked every check_every steps, at most max_steps), then
+ * set J' = m / rho0 per cell as the grid's volume.  Leaves the grid needing
+ * lbm_init.  *steps_out (may be NULL) receives the steps taken. */
+int lbm_noflow_adjust(lbm_grid *g, double tol, int64_t max_steps, int32_t check_every, int64_t *steps_out);
+
+/* Full state as FP64 particle numbers: P[q][n1][n2] (absolute N'_alpha, base
+ * added back) and the moving-wall side state side[2][2][c_max][n2]
+ * (wall low/high, field m / Ut^2, distance from the wall, column).  Either
+ * pointer may be NULL.  Synchronises. */
+int lbm_get_state(lbm_grid *g, double *P, double *side);
+int lbm_set_state(lbm_grid *g, const double *P, const double *side);
+
+/* Streaming map actually used by the step kernel: for every cell and
+ * direction, the source cell (i*n2 + j), source direction and crossed wall
+ * (0 none, 1 low, 2 high).  Arrays [n1*n2][q].  Synchronises. */
+int lbm_stream_map(lbm_grid *g, int32_t *src_cell, int32_t *src_dir, int32_t *wall);
+
+/* FP64 geometry precompute per cell: out[n1*n2][4 + 2q] = J, g^11, g^12,
+ * g^22, then for every alpha (A+^1, A+^2) with
+ * A+^i_alpha = sum_j c^j_alpha Theta^i_j(q + c_alpha, q).  Synchronises. */
+int lbm_geometry(lbm_grid *g, double *out);
+
+int lbm_synchronize(lbm_grid *g);
+void *lbm_stream(lbm_grid *g);
+
+/* Many grids advanced together: one launch per lattice and precision per step
+ * over a flattened table of row tiles; steps of a batch are captured in HIP
+ * graphs.  All grids must share the stream of grids[0]. */
+int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out);
+int lbm_batch_step(lbm_batch *b, int64_t n);
+void lbm_batch_destroy(lbm_batch *b);
+
+/* Launch configuration of the step kernels: waves per workgroup (1, 2 or 4;
+ * each wave covers 64 columns of one row) for a grid (and the batches made
+ * from it later).  0 restores the automatic choice. */
+int lbm_set_launch(lbm_grid *g, int32_t waves_per_block);
+
+/* Plain device copy kernel (for calibrating memory-traffic counters). */
+int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

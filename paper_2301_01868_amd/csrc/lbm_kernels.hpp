@@ -1,0 +1,382 @@
+// Device code of the curvilinear lattice Boltzmann library (gfx950).
+//
+// Method: Chekhlov, Staroselsky, Zhang, Chen, arXiv:2301.01868, Sec. 2 and
+// App. A-B.  The step works entirely in particle numbers N = J f, in which the
+// volume J cancels from the update:
+//   m = sum N,  m U^i = sum c^i N                          (Eqs. moments, vcomp)
+//   J F^i = -1/2 sum_a [A+^i_a N'_a(q, t-1) - A-^i_a N_a]  (Eq. compo-constr)
+//            + m a_ext^i,  with A-^i_a = -A+^i_{-a}
+//   Ut = U + J F / (2 m)
+//   J f^eq_a = m phi_a(U, Ut; g^ij)                         (Eq. equilibrium)
+//   J dPi^ij = -1/2 (1 - 1/(2 tau)) sum_a c^i_a (A+^j_a - A-^j_a) m phi_a   (Eq. delta-flux)
+//   dN_a = w_a [c.JF / T0 + (c^j c^k / T0 - delta^jk) J dPi^jk / T0]        (Eq. deltaN)
+//   N'_a = N_a - (N_a - m phi_a) / tau + dN_a                (Eqs. collide, lbe)
+// with A+^i_a(q) = sum_j c^j_a Theta^i_j(q + c_a, q) (Eq. gamma) precomputed.
+//
+// The equilibrium is evaluated in closed form, split into the part even and
+// the part odd in c for each +-c pair: with G = g^ij,
+//   phi_a = R_a + w_a [((c.Ut)^2 / T0 - |Ut|^2) / (2 T0)]                      (even)
+//         + w_a [(c.U)(1/T0 + (4 T0 - |c|^2)/(2 T0^2)) - c.G.Ut / T0
+//                + ((c.Ut)^2 - 3 T0 |Ut|^2)(c.Ut) / (6 T0^3)] + K_a (c.Ut)    (odd)
+//   R_a = w_a [1 + (c.G.c - |c|^2 - T0 (tr G - 2)) / (2 T0)],
+//   K_a = w_a (c.G.c - T0 tr G) / (2 T0^2),
+// which is the index sum of Eq. (equilibrium) contracted with the isotropic
+// Hermite tensors of a two-dimensional lattice.  Only the odd part enters the
+// momentum-flux correction (the c^i factor makes even parts cancel in pairs).
+//
+// Populations may be stored as offsets s_a = N_a - B_a(q) from a per-cell base
+// B (FP32 storage); the base terms are folded into per-row (or per-cell)
+// constants so that every sum runs over small numbers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_lattice.hpp"
+
+namespace lbm {
+
+enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_MOVING = 2 };
+
+// ---------------------------------------------------------------------------
+// step table layout (compute type T), one entry per row (row-invariant
+// geometry) or per cell
+// ---------------------------------------------------------------------------
+template <int Q>
+struct Tab {
+    static constexpr int G11 = 0, G12 = 1, G22 = 2, MB = 3, C1 = 4, C2 = 5, D0 = 6, PHIB0 = 7;
+    static constexpr int NP = npair<Q>();
+    __host__ __device__ static constexpr int A1(int a) { return 8 + 3 * (a - 1); }
+    __host__ __device__ static constexpr int A2(int a) { return 8 + 3 * (a - 1) + 1; }
+    __host__ __device__ static constexpr int DB(int a) { return 8 + 3 * (a - 1) + 2; }
+    __host__ __device__ static constexpr int K(int p) { return 8 + 3 * (Q - 1) + 3 * p; }
+    __host__ __device__ static constexpr int D(int p) { return 8 + 3 * (Q - 1) + 3 * p + 1; }
+    __host__ __device__ static constexpr int PHIB(int p) { return 8 + 3 * (Q - 1) + 3 * p + 2; }
+    static constexpr int W = 8 + 3 * (Q - 1) + 3 * NP;
+    static constexpr int STRIDE = (W + 3) & ~3;   // row stride, 16-byte multiple for FP32
+};
+
+// Per-instance launch descriptor (device memory, read with scalar loads).
+struct InstDesc {
+    void *P[2];          // population storage buffers, [Q][n1][pitch]
+    void *side[2];       // moving-wall side state, [2 walls][2 fields][hw][pitch]
+    const void *tab;     // step table
+    double *mom;         // moments output [5][ncell] (m, U1, U2, Ut1, Ut2)
+    const double *mB64;  // FP64 base mass per table entry
+    long long plane;     // elements per population plane (n1 * pitch)
+    int n1, n2, pitch, hw;
+    int periodic1, bc_lo, bc_hi, cell;
+    int iters, ncell, par0, pad;
+    double ut_lo, ut_hi, a1, a2, omega, kpi;
+};
+
+// Source of the pulled population N_a(i, .) (Eq. adv, App. B): row r and
+// direction beta of the post-collision field, and the crossed wall (0 none,
+// 1 low side, 2 high side).  Beyond a wall the source node is replaced by its
+// mirror image across the wall plane; no-slip takes the bounce-back direction,
+// a moving wall the specular one.  Requires n1 >= c_max.
+__host__ __device__ inline void pull_source(int i, int a, int n1, int periodic1, int bc_lo, int bc_hi, int &r,
+                                            int &beta, int &wall)
+{
+    const int ti = i - cx(a);
+    r = ti;
+    beta = a;
+    wall = 0;
+    if (ti < 0) {
+        if (periodic1) {
+            r = ti + n1;
+        } else {
+            r = -1 - ti;
+            wall = 1;
+            beta = (bc_lo == BC_NOSLIP) ? bounce(a) : specular(a);
+        }
+    } else if (ti >= n1) {
+        if (periodic1) {
+            r = ti - n1;
+        } else {
+            r = 2 * n1 - 1 - ti;
+            wall = 2;
+            beta = (bc_hi == BC_NOSLIP) ? bounce(a) : specular(a);
+        }
+    }
+}
+
+__device__ inline int wrap_col(int c, int n2)
+{
+    if (c < 0) c += n2;
+    if (c >= n2) c -= n2;
+    return c;
+}
+
+// Raw buffer access (MUBUF): the 128-bit resource holds the buffer base and
+// its size, so an access outside the buffer returns zero / is dropped instead
+// of faulting; the per-direction row offset goes in the scalar offset, the
+// column in the per-lane offset.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename S, typename T>
+__device__ inline T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(S) == 8) {
+        return (T)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    } else {
+        return (T)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+}
+template <typename S, typename T>
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v)
+{
+    if constexpr (sizeof(S) == 8) {
+        using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, (double)v), r, voff, soff, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, (float)v), r, voff, soff, 0);
+    }
+}
+
+// uniform (scalar-cache) view of a row table
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T, bool CELL>
+struct TabView {
+    const T *p;
+    int s;
+    __device__ inline T operator()(int f) const
+    {
+        if constexpr (CELL) {
+            return p[(size_t)f * s];
+        } else {
+            return ((cptr<T>)p)[f];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// the fused step (pull + moments + force + equilibrium + flux correction +
+// curvilinear correction + BGK + store), one cell per lane, one row segment of
+// 64 columns per wave; MOM = true computes and writes the moments instead of
+// colliding.
+// ---------------------------------------------------------------------------
+template <int Q, typename T, typename S, bool CELL, bool MOM>
+__global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts, const int4 *__restrict__ tiles,
+                                              int par)
+{
+    constexpr int CM = cmax<Q>();
+    constexpr int NP = npair<Q>();
+    constexpr double T0d = lattice_T0<Q>();
+    constexpr T T0 = (T)T0d;
+    using TB = Tab<Q>;
+
+    const int4 tl = tiles[blockIdx.x];
+    const InstDesc *__restrict__ d = insts + tl.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i = tl.y + wave;
+    const int n1 = d->n1, n2 = d->n2;
+    if (i >= n1) return;
+    const int j = tl.z + (int)(threadIdx.x & 63);
+    if (j >= n2) return;
+
+    const int pitch = d->pitch, hw = d->hw;
+    const long long plane = d->plane;
+    const int pin = (par ^ d->par0) & 1;
+    const S *__restrict__ Pin = (const S *)d->P[pin];
+    const int bclo = d->bc_lo, bchi = d->bc_hi, per1 = d->periodic1;
+
+    TabView<T, CELL> tb;
+    if constexpr (CELL) {
+        tb.p = (const T *)d->tab + (size_t)i * n2 + j;
+        tb.s = d->ncell;
+    } else {
+        tb.p = (const T *)d->tab + (size_t)i * TB::STRIDE;
+        tb.s = 1;
+    }
+
+    // byte offsets of the wrapped columns j - c2, c2 = -CM..CM (q2 is periodic)
+    constexpr uint32_t ES = sizeof(S);
+    uint32_t colb[2 * CM + 1];
+    if (n2 >= CM) {
+#pragma unroll
+        for (int k = -CM; k <= CM; ++k) colb[k + CM] = (uint32_t)wrap_col(j - k, n2) * ES;
+    } else {
+#pragma unroll
+        for (int k = -CM; k <= CM; ++k) colb[k + CM] = (uint32_t)(((j - k) % n2 + n2) % n2) * ES;
+    }
+    const uint32_t pbytes = (uint32_t)(plane * Q) * ES;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(Pin, pbytes);
+    const uint32_t plane_b = (uint32_t)plane * ES, pitch_b = (uint32_t)pitch * ES;
+
+    // ---- pull streaming with boundary sources ----
+    T n[Q], s[Q];
+    const bool interior = (i >= CM && i < n1 - CM);
+    if (interior) {
+        // rows whose whole stencil stays inside: source row i - c1, same direction
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            const uint32_t soff = (uint32_t)a * plane_b + (uint32_t)(i - cx(a)) * pitch_b;
+            n[a] = bload<S, T>(rin, colb[cy(a) + CM], soff);
+            if (a > 0) n[a] += tb(TB::DB(a));
+        }
+    } else {
+        const T *side_in = (const T *)d->side[pin];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            const int c2 = cy(a);
+            int r, beta, wall;
+            pull_source(i, a, n1, per1, bclo, bchi, r, beta, wall);
+            const uint32_t cb = colb[c2 + CM];
+            T v = bload<S, T>(rin, cb, (uint32_t)beta * plane_b + (uint32_t)r * pitch_b);
+            if (a > 0) v += tb(TB::DB(a));
+            if (c2 != 0 && wall != 0) {
+                const int sd = wall - 1;
+                if ((sd ? bchi : bclo) == BC_MOVING) {
+                    // App. B.3 moving-wall correction (tangential component)
+                    const int k = sd ? (n1 - 1 - r) : r;
+                    const T *sp = side_in + ((size_t)(sd * 2) * hw + k) * pitch + cb / ES;
+                    const T mz = sp[0];
+                    const T uz = sp[(size_t)hw * pitch];
+                    const T U0 = (T)(sd ? d->ut_hi : d->ut_lo);
+                    v += (T)(2.0 * weight<Q>(a) * c2 / T0d) * mz * (U0 - uz);
+                }
+            }
+            n[a] = v;
+        }
+    }
+    // own post-collision values N'(q, t-1) for the lagged force
+    const uint32_t jb = (uint32_t)j * ES;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) s[a] = bload<S, T>(rin, jb, (uint32_t)a * plane_b + (uint32_t)i * pitch_b);
+
+    // ---- moments ----
+    T dm = 0, mU1 = 0, mU2 = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        dm += n[a];
+        if (cx(a) != 0) mU1 += (T)cx(a) * n[a];
+        if (cy(a) != 0) mU2 += (T)cy(a) * n[a];
+    }
+    const T m = tb(TB::MB) + dm;
+    const T im = (T)1 / m;
+    const T U1 = mU1 * im, U2 = mU2 * im;
+
+    // ---- force: the part independent of the lagged own-cell values ----
+    T Ln1 = tb(TB::C1), Ln2 = tb(TB::C2);
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        Ln1 += tb(TB::A1(opp(a))) * n[a];
+        Ln2 += tb(TB::A2(opp(a))) * n[a];
+    }
+    const T ma1 = m * (T)d->a1, ma2 = m * (T)d->a2;
+    const T G11 = tb(TB::G11), G12 = tb(TB::G12), G22 = tb(TB::G22);
+    const T omega = (T)d->omega, kpi = (T)d->kpi;
+    const int iters = MOM ? 0 : d->iters;
+
+    T JF1, JF2, Ut1, Ut2;
+    for (int it = 0;; ++it) {
+        T L1 = Ln1, L2 = Ln2;
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            L1 += tb(TB::A1(a)) * s[a];
+            L2 += tb(TB::A2(a)) * s[a];
+        }
+        JF1 = (T)-0.5 * L1 + ma1;
+        JF2 = (T)-0.5 * L2 + ma2;
+        Ut1 = U1 + (T)0.5 * JF1 * im;
+        Ut2 = U2 + (T)0.5 * JF2 * im;
+        if constexpr (MOM) break;
+
+        // ---- equilibrium (pair form) and momentum-flux correction ----
+        const T GU1 = G11 * Ut1 + G12 * Ut2;
+        const T GU2 = G12 * Ut1 + G22 * Ut2;
+        const T uu = Ut1 * Ut1 + Ut2 * Ut2;
+        T Ev[NP], Od[NP];
+        T P11 = 0, P12 = 0, P21 = 0, P22 = 0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int a = pair_rep(p), b = opp(a);
+            const int c1 = cx(a), c2 = cy(a);
+            const double w = weight<Q>(a);
+            const double cc = (double)(c1 * c1 + c2 * c2);
+            const T cU = (T)c1 * U1 + (T)c2 * U2;
+            const T cUt = (T)c1 * Ut1 + (T)c2 * Ut2;
+            const T cGU = (T)c1 * GU1 + (T)c2 * GU2;
+            const T O = (T)(w * (1.0 / T0d + (4.0 * T0d - cc) / (2.0 * T0d * T0d))) * cU - (T)(w / T0d) * cGU +
+                        (T)(w / (6.0 * T0d * T0d * T0d)) * (cUt * cUt - (T)3 * T0 * uu) * cUt +
+                        tb(TB::K(p)) * cUt;
+            const T E = tb(TB::D(p)) + (T)(w / (2.0 * T0d)) * (cUt * cUt * (T)(1.0 / T0d) - uu);
+            Ev[p] = E;
+            Od[p] = O;
+            const T mO = m * O;
+            const T S1 = tb(TB::A1(a)) + tb(TB::A1(b));
+            const T S2 = tb(TB::A2(a)) + tb(TB::A2(b));
+            if (c1 != 0) {
+                P11 += (T)c1 * S1 * mO;
+                P12 += (T)c1 * S2 * mO;
+            }
+            if (c2 != 0) {
+                P21 += (T)c2 * S1 * mO;
+                P22 += (T)c2 * S2 * mO;
+            }
+        }
+        P11 *= kpi;
+        P12 *= kpi;
+        P21 *= kpi;
+        P22 *= kpi;
+        const T trP = P11 + P22;
+        const T P12s = P12 + P21;
+
+        // ---- curvilinear correction + BGK (offset form) ----
+        {
+            constexpr double w0 = weight<Q>(0);
+            const T feq0 = m * (tb(TB::D0) - (T)(w0 / (2.0 * T0d)) * uu) + dm * tb(TB::PHIB0);
+            s[0] = n[0] - omega * (n[0] - feq0) - (T)(w0 / T0d) * trP;
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int a = pair_rep(p), b = opp(a);
+            const int c1 = cx(a), c2 = cy(a);
+            const double w = weight<Q>(a);
+            const T phib = tb(TB::PHIB(p));
+            const T feqA = m * (Ev[p] + Od[p]) + dm * phib;
+            const T feqB = m * (Ev[p] - Od[p]) + dm * phib;
+            const T odd = (T)(w / T0d) * ((T)c1 * JF1 + (T)c2 * JF2);
+            const T even = (T)(w / T0d) * (((T)(c1 * c1) * P11 + (T)(c1 * c2) * P12s + (T)(c2 * c2) * P22) *
+                                               (T)(1.0 / T0d) -
+                                           trP);
+            s[a] = n[a] - omega * (n[a] - feqA) + even + odd;
+            s[b] = n[b] - omega * (n[b] - feqB) + even - odd;
+        }
+        if (it >= iters) break;
+    }
+
+    if constexpr (MOM) {
+        const int c = i * n2 + j;
+        const int e = CELL ? c : i;
+        double *mo = d->mom;
+        const size_t nc = (size_t)d->ncell;
+        mo[c] = d->mB64[e] + (double)dm;
+        mo[nc + c] = (double)U1;
+        mo[2 * nc + c] = (double)U2;
+        mo[3 * nc + c] = (double)Ut1;
+        mo[4 * nc + c] = (double)Ut2;
+    } else {
+        const __amdgpu_buffer_rsrc_t rout = make_rsrc(d->P[pin ^ 1], pbytes);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) bstore<S, T>(rout, jb, (uint32_t)a * plane_b + (uint32_t)i * pitch_b, s[a]);
+        // side state of the moving walls: m and Ut^2 of the rows a wall pulls from
+        T *side_out = (T *)d->side[pin ^ 1];
+        if (bclo == BC_MOVING && i < hw) {
+            side_out[((size_t)0 * hw + i) * pitch + j] = m;
+            side_out[((size_t)1 * hw + i) * pitch + j] = Ut2;
+        }
+        if (bchi == BC_MOVING && i >= n1 - hw) {
+            const int k = n1 - 1 - i;
+            side_out[((size_t)2 * hw + k) * pitch + j] = m;
+            side_out[((size_t)3 * hw + k) * pitch + j] = Ut2;
+        }
+    }
+}
+
+} // namespace lbm

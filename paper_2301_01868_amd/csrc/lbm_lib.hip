@@ -1,0 +1,926 @@
+// Host side of the C ABI declared in include/lbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_setup.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    int steps = 0;
+};
+
+} // namespace
+
+struct lbm_grid {
+    lbm_grid_desc desc{};
+    int q = 0, n1 = 0, n2 = 0, h = 0, pitch = 0, hw = 0, ncell = 0;
+    int row = 1, nent = 0;
+    int precision = LBM_FP64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool has_alloc = false;
+    lbm_allocator alloc{};
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    // device buffers
+    void *P[2] = {nullptr, nullptr};
+    void *side[2] = {nullptr, nullptr};
+    void *tab = nullptr;
+    double *base = nullptr, *mB64 = nullptr;
+    double *X = nullptr, *Y = nullptr;
+    double *Jgeo = nullptr, *Jused = nullptr, *G3 = nullptr, *g4 = nullptr, *xc = nullptr, *yc = nullptr;
+    double *mom = nullptr, *snap = nullptr, *partial = nullptr, *redout = nullptr;
+    InstDesc *d_inst = nullptr;
+    int4 *d_tiles = nullptr;
+    int ntiles = 0, wpb = 4;
+    InstDesc h_inst{};
+    int64_t step = 0;
+    int par = 0;
+    bool inited = false;
+    double mass0 = 0.0;
+    bool snap_valid = false;
+    int64_t snap_step = 0;
+    GraphCache graph[2];
+    std::string err;
+};
+
+struct lbm_batch {
+    std::vector<lbm_grid *> grids;
+    hipStream_t stream = nullptr;
+    struct Group {
+        int q = 0, precision = 0, cell = 0;
+        InstDesc *d_inst = nullptr;
+        int4 *d_tiles = nullptr;
+        int ntiles = 0, wpb = 4;
+    };
+    std::vector<Group> groups;
+    std::vector<void *> allocs;
+    GraphCache graph;
+    int64_t step = 0;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static int fail(lbm_grid *g, int code, const std::string &msg)
+{
+    if (g) g->err = msg;
+    g_last_error = msg;
+    return code;
+}
+
+#define HIPCHK(g, call)                                                                              \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail((g), LBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+static void *dalloc(lbm_grid *g, size_t bytes)
+{
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (g->has_alloc) {
+        p = g->alloc.alloc(bytes, g->alloc.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) {
+        g->allocs.push_back(p);
+        g->bytes += bytes;
+    }
+    return p;
+}
+
+static void dfree(lbm_grid *g, void *p)
+{
+    if (!p) return;
+    auto it = std::find(g->allocs.begin(), g->allocs.end(), p);
+    if (it != g->allocs.end()) g->allocs.erase(it);
+    if (g->has_alloc) g->alloc.free(p, g->alloc.ctx);
+    else (void)hipFree(p);
+}
+
+static size_t store_size(int precision) { return precision == LBM_FP64 ? sizeof(double) : sizeof(float); }
+static size_t comp_size(int precision) { return precision == LBM_FP64 ? sizeof(double) : sizeof(float); }
+
+static dim3 cell_grid(int n1, int n2) { return dim3((n2 + 127) / 128, n1); }
+
+// kernel dispatch tables -------------------------------------------------------
+typedef void (*StepFn)(const InstDesc *, const int4 *, int);
+
+template <int Q>
+static StepFn step_fn(int precision, int cell, int mom)
+{
+    if (precision == LBM_FP64) {
+        if (cell) return mom ? k_step<Q, double, double, true, true> : k_step<Q, double, double, true, false>;
+        return mom ? k_step<Q, double, double, false, true> : k_step<Q, double, double, false, false>;
+    }
+    if (cell) return mom ? k_step<Q, float, float, true, true> : k_step<Q, float, float, true, false>;
+    return mom ? k_step<Q, float, float, false, true> : k_step<Q, float, float, false, false>;
+}
+
+static StepFn pick_step(int q, int precision, int cell, int mom)
+{
+    return q == 9 ? step_fn<9>(precision, cell, mom) : step_fn<21>(precision, cell, mom);
+}
+
+static std::vector<int4> make_tiles(int inst, int n1, int n2, int wpb)
+{
+    std::vector<int4> nat;
+    const int ncs = (n2 + 63) / 64;
+    for (int r0 = 0; r0 < n1; r0 += wpb)
+        for (int cs = 0; cs < ncs; ++cs) nat.push_back(make_int4(inst, r0, cs * 64, 0));
+    return nat;
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2);
+// order the tile table so that XCD x gets one contiguous slab of tiles, in
+// their natural (row-major) order, so neighbouring rows share an L2.
+static std::vector<int4> xcd_order(const std::vector<int4> &nat, int dummy_row)
+{
+    const size_t nt = nat.size();
+    const size_t nt8 = (nt + 7) / 8 * 8;
+    const size_t chunk = nt8 / 8;
+    std::vector<int4> out(nt8);
+    for (size_t b = 0; b < nt8; ++b) {
+        const size_t x = b % 8, y = b / 8;
+        const size_t t = x * chunk + y;
+        out[b] = t < nt ? nat[t] : make_int4(nat.empty() ? 0 : nat[0].x, dummy_row, 0, 0);
+    }
+    return out;
+}
+
+static int upload_inst(lbm_grid *g)
+{
+    HIPCHK(g, hipMemcpyAsync(g->d_inst, &g->h_inst, sizeof(InstDesc), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    return LBM_OK;
+}
+
+static void drop_graphs(lbm_grid *g)
+{
+    for (auto &gc : g->graph) {
+        if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+        gc.exec = nullptr;
+        gc.steps = 0;
+    }
+}
+
+static int build_tiles(lbm_grid *g)
+{
+    auto nat = make_tiles(0, g->n1, g->n2, g->wpb);
+    auto ord = xcd_order(nat, g->n1);
+    if (g->d_tiles) dfree(g, g->d_tiles);
+    g->d_tiles = (int4 *)dalloc(g, ord.size() * sizeof(int4));
+    if (!g->d_tiles) return fail(g, LBM_ENOMEM, "tile table allocation failed");
+    g->ntiles = (int)ord.size();
+    HIPCHK(g, hipMemcpyAsync(g->d_tiles, ord.data(), ord.size() * sizeof(int4), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    drop_graphs(g);
+    return LBM_OK;
+}
+
+static int launch_step(lbm_grid *g, int par, int mom)
+{
+    StepFn fn = pick_step(g->q, g->precision, !g->row, mom);
+    hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), 0, g->stream, (const InstDesc *)g->d_inst,
+                       (const int4 *)g->d_tiles, par);
+    HIPCHK(g, hipGetLastError());
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// API
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int lbm_lattice(int32_t q, int32_t *cxo, int32_t *cyo, double *w, double *T0)
+{
+    if (q != 9 && q != 21) return fail(nullptr, LBM_EINVAL, "q must be 9 or 21");
+    for (int a = 0; a < q; ++a) {
+        if (cxo) cxo[a] = cx(a);
+        if (cyo) cyo[a] = cy(a);
+        if (w) w[a] = q == 9 ? weight<9>(a) : weight<21>(a);
+    }
+    if (T0) *T0 = q == 9 ? lattice_T0<9>() : lattice_T0<21>();
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_grid *g)
+{
+    if (g && !g->err.empty()) return g->err.c_str();
+    return g_last_error.c_str();
+}
+
+void lbm_grid_destroy(lbm_grid *g)
+{
+    if (!g) return;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    drop_graphs(g);
+    auto all = g->allocs;
+    for (void *p : all) dfree(g, p);
+    if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+}
+
+int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
+{
+    if (!desc || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    *out = nullptr;
+    const lbm_grid_desc &D = *desc;
+    if (D.q != 9 && D.q != 21) return fail(nullptr, LBM_EINVAL, "q must be 9 or 21");
+    const int cm = D.q == 9 ? 1 : 3;
+    if (D.n1 < 1 || D.n2 < 1) return fail(nullptr, LBM_EINVAL, "n1 and n2 must be positive");
+    if (D.halo < cm + 1) return fail(nullptr, LBM_EINVAL, "halo must be at least c_max + 1");
+    if (!D.x || !D.y) return fail(nullptr, LBM_EINVAL, "mapping coordinates missing");
+    if (!(D.tau > 0.5)) return fail(nullptr, LBM_EINVAL, "tau must exceed 1/2");
+    const bool per1 = D.bc_lo == LBM_PERIODIC || D.bc_hi == LBM_PERIODIC;
+    if (per1 && D.bc_lo != D.bc_hi) return fail(nullptr, LBM_EINVAL, "a periodic q1 side must be paired");
+    for (int b : {D.bc_lo, D.bc_hi})
+        if (b != LBM_PERIODIC && b != LBM_NOSLIP && b != LBM_MOVING) return fail(nullptr, LBM_EINVAL, "unknown boundary kind");
+    if (D.n1 < cm) return fail(nullptr, LBM_EINVAL, "n1 must be at least c_max");
+    if (D.precision != LBM_FP64 && D.precision != LBM_FP32) return fail(nullptr, LBM_EINVAL, "unknown precision");
+    if (D.iterations < 0 || D.iterations > 16) return fail(nullptr, LBM_EINVAL, "iterations must be in 0..16");
+    if ((int64_t)D.n1 * D.n2 > (int64_t)1 << 30) return fail(nullptr, LBM_EINVAL, "grid too large");
+    {   // one population buffer must stay below 2 GiB (32-bit buffer offsets)
+        const int64_t pitch = D.n2 >= 64 ? (D.n2 + 63) / 64 * 64 : D.n2;
+        if ((int64_t)D.q * D.n1 * pitch * (D.precision == LBM_FP64 ? 8 : 4) >= ((int64_t)1 << 31))
+            return fail(nullptr, LBM_EINVAL, "grid too large for one population buffer (2 GiB)");
+    }
+
+    lbm_grid *g = new lbm_grid();
+    g->desc = D;
+    g->desc.x = g->desc.y = nullptr;
+    g->q = D.q;
+    g->n1 = D.n1;
+    g->n2 = D.n2;
+    g->h = D.halo;
+    g->hw = cm;
+    g->ncell = D.n1 * D.n2;
+    g->pitch = D.n2 >= 64 ? (D.n2 + 63) / 64 * 64 : D.n2;
+    g->precision = D.precision;
+    if (D.alloc) {
+        g->has_alloc = true;
+        g->alloc = *D.alloc;
+    }
+    if (D.stream) {
+        g->stream = (hipStream_t)D.stream;
+    } else {
+        if (hipStreamCreate(&g->stream) != hipSuccess) {
+            delete g;
+            return fail(nullptr, LBM_EDEVICE, "hipStreamCreate failed");
+        }
+        g->own_stream = true;
+    }
+    auto bail = [&](int code, const std::string &m) {
+        g_last_error = m;
+        lbm_grid_destroy(g);
+        return code;
+    };
+
+    const int q = g->q, n1 = g->n1, n2 = g->n2, h = g->h, nc = g->ncell;
+    const int H1 = n1 + 2 * h, H2 = n2 + 2 * h;
+    const size_t nh = (size_t)H1 * H2;
+    const int nf = geo_fields(q);
+
+    // FP64 persistent per-cell arrays
+    g->X = (double *)dalloc(g, nh * 8);
+    g->Y = (double *)dalloc(g, nh * 8);
+    g->Jgeo = (double *)dalloc(g, (size_t)nc * 8);
+    g->Jused = (double *)dalloc(g, (size_t)nc * 8);
+    g->G3 = (double *)dalloc(g, (size_t)nc * 3 * 8);
+    g->g4 = (double *)dalloc(g, (size_t)nc * 4 * 8);
+    g->xc = (double *)dalloc(g, (size_t)nc * 8);
+    g->yc = (double *)dalloc(g, (size_t)nc * 8);
+    g->mom = (double *)dalloc(g, (size_t)nc * 5 * 8);
+    g->snap = (double *)dalloc(g, (size_t)nc * 2 * 8);
+    g->partial = (double *)dalloc(g, (size_t)RED_BLOCKS * RED_NF * 8);
+    g->redout = (double *)dalloc(g, 8 * 8);
+    g->d_inst = (InstDesc *)dalloc(g, sizeof(InstDesc));
+    double *tg = (double *)dalloc(g, nh * 4 * 8);
+    double *geo = (double *)dalloc(g, (size_t)nc * nf * 8);
+    int *flag = (int *)dalloc(g, 2 * sizeof(int));
+    if (!g->X || !g->Y || !g->Jgeo || !g->Jused || !g->G3 || !g->g4 || !g->xc || !g->yc || !g->mom || !g->snap ||
+        !g->partial || !g->redout || !g->d_inst || !tg || !geo || !flag)
+        return bail(LBM_ENOMEM, "device allocation failed (geometry)");
+
+    hipStream_t st = g->stream;
+#define HIPB(call)                                                                                       \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) return bail(LBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+    HIPB(hipMemcpyAsync(g->X, D.x, nh * 8, hipMemcpyHostToDevice, st));
+    HIPB(hipMemcpyAsync(g->Y, D.y, nh * 8, hipMemcpyHostToDevice, st));
+    // cell centres
+    for (int i = 0; i < n1; ++i) {
+        HIPB(hipMemcpy2DAsync(g->xc + (size_t)i * n2, n2 * 8, D.x + (size_t)(i + h) * H2 + h, H2 * 8, n2 * 8, 1,
+                              hipMemcpyHostToDevice, st));
+        HIPB(hipMemcpy2DAsync(g->yc + (size_t)i * n2, n2 * 8, D.y + (size_t)(i + h) * H2 + h, H2 * 8, n2 * 8, 1,
+                              hipMemcpyHostToDevice, st));
+    }
+    // geometry precompute (FP64)
+    hipLaunchKernelGGL(k_tangent, dim3((H2 + 127) / 128, H1), dim3(128), 0, st, g->X, g->Y, H1, H2, tg);
+    if (q == 9)
+        hipLaunchKernelGGL(k_geom_cell<9>, cell_grid(n1, n2), dim3(128), 0, st, tg, n1, n2, h, geo, g->Jgeo, g->g4);
+    else
+        hipLaunchKernelGGL(k_geom_cell<21>, cell_grid(n1, n2), dim3(128), 0, st, tg, n1, n2, h, geo, g->Jgeo, g->g4);
+    HIPB(hipGetLastError());
+    HIPB(hipMemcpyAsync(g->G3, geo + (size_t)GEO_G11 * nc, (size_t)nc * 3 * 8, hipMemcpyDeviceToDevice, st));
+    HIPB(hipMemcpyAsync(g->Jused, g->Jgeo, (size_t)nc * 8, hipMemcpyDeviceToDevice, st));
+    int hflag[2] = {0, 0};
+    HIPB(hipMemcpyAsync(flag, hflag, sizeof hflag, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_rowcheck, cell_grid(n1, n2), dim3(128), 0, st, geo, n1, n2, nf, 1e-11, flag);
+    HIPB(hipGetLastError());
+    HIPB(hipMemcpyAsync(hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, st));
+    HIPB(hipStreamSynchronize(st));
+    if (hflag[1]) return bail(LBM_EINVAL, "the mapping has J <= 0 (or non-finite geometry) in some cell");
+    g->row = (D.geometry == LBM_GEOM_CELL) ? 0 : (hflag[0] ? 0 : 1);
+    g->nent = g->row ? n1 : nc;
+    if (g->row) {
+        hipLaunchKernelGGL(k_canon_rows, cell_grid(n1, n2), dim3(128), 0, st, n1, n2, g->Jgeo, g->G3);
+        HIPB(hipGetLastError());
+        HIPB(hipMemcpyAsync(g->Jused, g->Jgeo, (size_t)nc * 8, hipMemcpyDeviceToDevice, st));
+    }
+
+    // tables
+    TableArgs ta{};
+    ta.geo = geo;
+    ta.n1 = n1;
+    ta.n2 = n2;
+    ta.ncell = nc;
+    ta.cellmode = !g->row;
+    ta.nent = g->nent;
+    ta.periodic1 = per1;
+    ta.bc_lo = D.bc_lo;
+    ta.bc_hi = D.bc_hi;
+    ta.base_kind = (D.precision == LBM_FP64) ? 2 : D.offset_base;
+    ta.rho0 = D.rho0;
+    g->base = (double *)dalloc(g, (size_t)g->nent * q * 8);
+    g->mB64 = (double *)dalloc(g, (size_t)g->nent * 8);
+    const int tabw = q == 9 ? Tab<9>::STRIDE : Tab<21>::STRIDE;
+    g->tab = dalloc(g, (size_t)g->nent * tabw * comp_size(g->precision));
+    if (!g->base || !g->mB64 || !g->tab) return bail(LBM_ENOMEM, "device allocation failed (tables)");
+    const dim3 eb((g->nent + 127) / 128);
+    if (q == 9) {
+        hipLaunchKernelGGL(k_base<9>, eb, dim3(128), 0, st, ta, g->base, g->mB64);
+        if (g->precision == LBM_FP64)
+            hipLaunchKernelGGL((k_table<9, double>), eb, dim3(128), 0, st, ta, g->base, g->mB64, (double *)g->tab);
+        else
+            hipLaunchKernelGGL((k_table<9, float>), eb, dim3(128), 0, st, ta, g->base, g->mB64, (float *)g->tab);
+    } else {
+        hipLaunchKernelGGL(k_base<21>, eb, dim3(128), 0, st, ta, g->base, g->mB64);
+        if (g->precision == LBM_FP64)
+            hipLaunchKernelGGL((k_table<21, double>), eb, dim3(128), 0, st, ta, g->base, g->mB64, (double *)g->tab);
+        else
+            hipLaunchKernelGGL((k_table<21, float>), eb, dim3(128), 0, st, ta, g->base, g->mB64, (float *)g->tab);
+    }
+    HIPB(hipGetLastError());
+
+    // populations and side state
+    const size_t plane = (size_t)n1 * g->pitch;
+    for (int b = 0; b < 2; ++b) {
+        g->P[b] = dalloc(g, plane * q * store_size(g->precision));
+        g->side[b] = dalloc(g, (size_t)4 * g->hw * g->pitch * comp_size(g->precision));
+        if (!g->P[b] || !g->side[b]) return bail(LBM_ENOMEM, "device allocation failed (populations)");
+        HIPB(hipMemsetAsync(g->P[b], 0, plane * q * store_size(g->precision), st));
+        HIPB(hipMemsetAsync(g->side[b], 0, (size_t)4 * g->hw * g->pitch * comp_size(g->precision), st));
+    }
+    HIPB(hipStreamSynchronize(st));
+    dfree(g, tg);
+    dfree(g, geo);
+    dfree(g, flag);
+
+    InstDesc &I = g->h_inst;
+    I.P[0] = g->P[0];
+    I.P[1] = g->P[1];
+    I.side[0] = g->side[0];
+    I.side[1] = g->side[1];
+    I.tab = g->tab;
+    I.mom = g->mom;
+    I.mB64 = g->mB64;
+    I.plane = (long long)plane;
+    I.n1 = n1;
+    I.n2 = n2;
+    I.pitch = g->pitch;
+    I.hw = g->hw;
+    I.periodic1 = per1;
+    I.bc_lo = per1 ? BC_PERIODIC : D.bc_lo;
+    I.bc_hi = per1 ? BC_PERIODIC : D.bc_hi;
+    I.cell = !g->row;
+    I.iters = D.iterations;
+    I.ncell = nc;
+    I.par0 = 0;
+    I.ut_lo = D.ut_lo;
+    I.ut_hi = D.ut_hi;
+    I.a1 = D.accel[0];
+    I.a2 = D.accel[1];
+    I.omega = 1.0 / D.tau;
+    I.kpi = -(1.0 - 1.0 / (2.0 * D.tau));
+    if (upload_inst(g) != LBM_OK) return bail(LBM_EDEVICE, g->err);
+    g->wpb = 4;
+    if (build_tiles(g) != LBM_OK) return bail(LBM_EDEVICE, g->err);
+    HIPB(hipStreamSynchronize(st));
+#undef HIPB
+    *out = g;
+    return LBM_OK;
+}
+
+int lbm_grid_info_get(const lbm_grid *g, lbm_grid_info *out)
+{
+    if (!g || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    out->q = g->q;
+    out->n1 = g->n1;
+    out->n2 = g->n2;
+    out->pitch = g->pitch;
+    out->precision = g->precision;
+    out->row_tables = g->row;
+    out->step = g->step;
+    out->bytes_per_update = 2.0 * g->q * (double)store_size(g->precision);
+    out->device_bytes = g->bytes;
+    return LBM_OK;
+}
+
+int lbm_set_launch(lbm_grid *g, int32_t wpb)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    if (wpb == 0) wpb = 4;
+    if (wpb != 1 && wpb != 2 && wpb != 4) return fail(g, LBM_EINVAL, "waves per block must be 1, 2 or 4");
+    g->wpb = wpb;
+    return build_tiles(g);
+}
+
+int lbm_set_volume(lbm_grid *g, const double *J)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    if (J) {
+        for (int c = 0; c < g->ncell; ++c)
+            if (!(J[c] > 0.0)) return fail(g, LBM_EINVAL, "volume must be positive");
+        HIPCHK(g, hipMemcpyAsync(g->Jused, J, (size_t)g->ncell * 8, hipMemcpyHostToDevice, g->stream));
+    } else {
+        HIPCHK(g, hipMemcpyAsync(g->Jused, g->Jgeo, (size_t)g->ncell * 8, hipMemcpyDeviceToDevice, g->stream));
+    }
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    return LBM_OK;
+}
+
+static int reduce(lbm_grid *g, int update_snap, double out[RED_NF]);
+
+int lbm_init(lbm_grid *g, const double *u0)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    double *du = nullptr;
+    if (u0) {
+        du = (double *)dalloc(g, (size_t)g->ncell * 2 * 8);
+        if (!du) return fail(g, LBM_ENOMEM, "allocation failed");
+        HIPCHK(g, hipMemcpyAsync(du, u0, (size_t)g->ncell * 2 * 8, hipMemcpyHostToDevice, g->stream));
+    }
+    g->par = 0;
+    g->step = 0;
+    InitArgs ia{g->G3, g->Jused, du, g->base, g->desc.rho0, !g->row, 0};
+    const dim3 gr = cell_grid(g->n1, g->n2);
+    if (g->q == 9) {
+        if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_init<9, double, double>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
+        else hipLaunchKernelGGL((k_init<9, float, float>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
+    } else {
+        if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_init<21, double, double>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
+        else hipLaunchKernelGGL((k_init<21, float, float>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
+    }
+    HIPCHK(g, hipGetLastError());
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    if (du) dfree(g, du);
+    g->inited = true;
+    g->snap_valid = false;
+    double r[RED_NF];
+    int rc = reduce(g, 1, r);
+    if (rc != LBM_OK) return rc;
+    g->mass0 = r[0];
+    g->snap_valid = true;
+    g->snap_step = 0;
+    return LBM_OK;
+}
+
+static int capture_graph(lbm_grid *g, int start_par, int steps)
+{
+    GraphCache &gc = g->graph[start_par];
+    if (gc.exec && gc.steps == steps) return LBM_OK;
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    gc.exec = nullptr;
+    hipGraph_t graph = nullptr;
+    HIPCHK(g, hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+    int par = start_par;
+    for (int s = 0; s < steps; ++s) {
+        StepFn fn = pick_step(g->q, g->precision, !g->row, 0);
+        hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), 0, g->stream, (const InstDesc *)g->d_inst,
+                           (const int4 *)g->d_tiles, par);
+        par ^= 1;
+    }
+    HIPCHK(g, hipStreamEndCapture(g->stream, &graph));
+    HIPCHK(g, hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    gc.steps = steps;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_grid *g, int64_t n)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    if (!g->inited) return fail(g, LBM_ESTATE, "lbm_init must be called before lbm_step");
+    if (n < 0) return fail(g, LBM_EINVAL, "negative step count");
+    const int GS = 32;   // steps per captured graph (even: the buffer parity returns)
+    if (n >= GS) {
+        int rc = capture_graph(g, g->par, GS);
+        if (rc != LBM_OK) return rc;
+        const int64_t reps = n / GS;
+        for (int64_t k = 0; k < reps; ++k) HIPCHK(g, hipGraphLaunch(g->graph[g->par].exec, g->stream));
+        g->step += reps * GS;
+        n -= reps * GS;
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        int rc = launch_step(g, g->par, 0);
+        if (rc != LBM_OK) return rc;
+        g->par ^= 1;
+        g->step += 1;
+    }
+    return LBM_OK;
+}
+
+static int run_moments(lbm_grid *g) { return launch_step(g, g->par, 1); }
+
+static int reduce(lbm_grid *g, int update_snap, double out[RED_NF])
+{
+    int rc = run_moments(g);
+    if (rc != LBM_OK) return rc;
+    ReduceArgs ra{g->mom, g->snap, g->g4, g->xc, g->yc, g->ncell, update_snap, g->partial};
+    hipLaunchKernelGGL(k_reduce, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, g->stream, ra);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, g->stream, (const double *)g->partial, g->redout);
+    HIPCHK(g, hipGetLastError());
+    HIPCHK(g, hipMemcpyAsync(out, g->redout, RED_NF * 8, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    return LBM_OK;
+}
+
+int lbm_residual(lbm_grid *g, lbm_resid *out)
+{
+    if (!g || !out) return fail(g, LBM_EINVAL, "null argument");
+    if (!g->inited) return fail(g, LBM_ESTATE, "lbm_init must be called first");
+    double r[RED_NF];
+    int rc = reduce(g, 1, r);
+    if (rc != LBM_OK) return rc;
+    const int64_t K = g->step - g->snap_step;
+    out->step = g->step;
+    out->mass = r[0];
+    out->mass_rel_drift = g->mass0 != 0.0 ? (r[0] - g->mass0) / g->mass0 : 0.0;
+    out->residual = (g->snap_valid && K > 0 && r[2] > 0.0) ? std::sqrt(r[1]) / ((double)K * std::sqrt(r[2]))
+                                                            : INFINITY;
+    out->kinetic_energy = r[3];
+    out->angular_momentum = r[4];
+    out->bad_cells = (int64_t)r[5];
+    g->snap_valid = true;
+    g->snap_step = g->step;
+    if (out->bad_cells > 0) return fail(g, LBM_EUNSTABLE, "non-finite values or m <= 0 in some cells");
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_grid *g, double *m, double *U, double *Ut)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    if (!g->inited) return fail(g, LBM_ESTATE, "lbm_init must be called first");
+    int rc = run_moments(g);
+    if (rc != LBM_OK) return rc;
+    const size_t nc = g->ncell;
+    std::vector<double> h(nc * 5);
+    HIPCHK(g, hipMemcpyAsync(h.data(), g->mom, nc * 5 * 8, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    for (size_t c = 0; c < nc; ++c) {
+        if (m) m[c] = h[c];
+        if (U) {
+            U[2 * c] = h[nc + c];
+            U[2 * c + 1] = h[2 * nc + c];
+        }
+        if (Ut) {
+            Ut[2 * c] = h[3 * nc + c];
+            Ut[2 * c + 1] = h[4 * nc + c];
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_noflow_adjust(lbm_grid *g, double tol, int64_t max_steps, int32_t check_every, int64_t *steps_out)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    if (check_every <= 0 || max_steps <= 0 || !(tol > 0)) return fail(g, LBM_EINVAL, "bad no-flow parameters");
+    const InstDesc saved = g->h_inst;
+    g->h_inst.ut_lo = g->h_inst.ut_hi = 0.0;
+    g->h_inst.a1 = g->h_inst.a2 = 0.0;
+    int rc = upload_inst(g);
+    if (rc == LBM_OK) rc = lbm_set_volume(g, nullptr);
+    if (rc == LBM_OK) rc = lbm_init(g, nullptr);
+    int64_t done = 0;
+    lbm_resid res{};
+    while (rc == LBM_OK && done < max_steps) {
+        rc = lbm_step(g, check_every);
+        done += check_every;
+        if (rc == LBM_OK) rc = lbm_residual(g, &res);
+        if (rc == LBM_OK && res.residual < tol) break;
+    }
+    if (rc == LBM_OK) {
+        rc = run_moments(g);
+        if (rc == LBM_OK) {
+            hipLaunchKernelGGL(k_volume_from_mass, dim3((g->ncell + 255) / 256), dim3(256), 0, g->stream,
+                               (const double *)g->mom, g->desc.rho0, g->ncell, g->Jused);
+            if (hipGetLastError() != hipSuccess) rc = fail(g, LBM_EDEVICE, "volume kernel failed");
+        }
+    }
+    g->h_inst = saved;
+    const int rc2 = upload_inst(g);
+    if (hipStreamSynchronize(g->stream) != hipSuccess && rc == LBM_OK) rc = fail(g, LBM_EDEVICE, "sync failed");
+    g->inited = false;
+    if (steps_out) *steps_out = done;
+    return rc != LBM_OK ? rc : rc2;
+}
+
+int lbm_get_state(lbm_grid *g, double *P, double *side)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    const dim3 gr = cell_grid(g->n1, g->n2);
+    if (P) {
+        double *tmp = (double *)dalloc(g, (size_t)g->ncell * g->q * 8);
+        if (!tmp) return fail(g, LBM_ENOMEM, "allocation failed");
+        if (g->q == 9) {
+            if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_out<9, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+            else hipLaunchKernelGGL((k_state_out<9, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+        } else {
+            if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_out<21, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+            else hipLaunchKernelGGL((k_state_out<21, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+        }
+        HIPCHK(g, hipGetLastError());
+        HIPCHK(g, hipMemcpyAsync(P, tmp, (size_t)g->ncell * g->q * 8, hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(g, hipStreamSynchronize(g->stream));
+        dfree(g, tmp);
+    }
+    if (side) {
+        const size_t ns = (size_t)4 * g->hw * g->n2;
+        double *tmp = (double *)dalloc(g, ns * 8);
+        if (!tmp) return fail(g, LBM_ENOMEM, "allocation failed");
+        const dim3 sg((g->n2 + 127) / 128, 4 * g->hw);
+        if (g->precision == LBM_FP64) hipLaunchKernelGGL(k_side_io<double>, sg, dim3(128), 0, g->stream, g->d_inst, g->par, tmp, 0);
+        else hipLaunchKernelGGL(k_side_io<float>, sg, dim3(128), 0, g->stream, g->d_inst, g->par, tmp, 0);
+        HIPCHK(g, hipGetLastError());
+        HIPCHK(g, hipMemcpyAsync(side, tmp, ns * 8, hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(g, hipStreamSynchronize(g->stream));
+        dfree(g, tmp);
+    }
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_grid *g, const double *P, const double *side)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    const dim3 gr = cell_grid(g->n1, g->n2);
+    if (P) {
+        double *tmp = (double *)dalloc(g, (size_t)g->ncell * g->q * 8);
+        if (!tmp) return fail(g, LBM_ENOMEM, "allocation failed");
+        HIPCHK(g, hipMemcpyAsync(tmp, P, (size_t)g->ncell * g->q * 8, hipMemcpyHostToDevice, g->stream));
+        if (g->q == 9) {
+            if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_in<9, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+            else hipLaunchKernelGGL((k_state_in<9, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+        } else {
+            if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_in<21, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+            else hipLaunchKernelGGL((k_state_in<21, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+        }
+        HIPCHK(g, hipGetLastError());
+        HIPCHK(g, hipStreamSynchronize(g->stream));
+        dfree(g, tmp);
+    }
+    if (side) {
+        const size_t ns = (size_t)4 * g->hw * g->n2;
+        double *tmp = (double *)dalloc(g, ns * 8);
+        if (!tmp) return fail(g, LBM_ENOMEM, "allocation failed");
+        HIPCHK(g, hipMemcpyAsync(tmp, side, ns * 8, hipMemcpyHostToDevice, g->stream));
+        const dim3 sg((g->n2 + 127) / 128, 4 * g->hw);
+        if (g->precision == LBM_FP64) hipLaunchKernelGGL(k_side_io<double>, sg, dim3(128), 0, g->stream, g->d_inst, g->par, tmp, 1);
+        else hipLaunchKernelGGL(k_side_io<float>, sg, dim3(128), 0, g->stream, g->d_inst, g->par, tmp, 1);
+        HIPCHK(g, hipGetLastError());
+        HIPCHK(g, hipStreamSynchronize(g->stream));
+        dfree(g, tmp);
+    }
+    g->inited = true;
+    return LBM_OK;
+}
+
+int lbm_stream_map(lbm_grid *g, int32_t *src_cell, int32_t *src_dir, int32_t *wall)
+{
+    if (!g || !src_cell || !src_dir || !wall) return fail(g, LBM_EINVAL, "null argument");
+    const size_t n = (size_t)g->ncell * g->q;
+    int *t = (int *)dalloc(g, n * 3 * sizeof(int));
+    if (!t) return fail(g, LBM_ENOMEM, "allocation failed");
+    const dim3 gr = cell_grid(g->n1, g->n2);
+    if (g->q == 9) hipLaunchKernelGGL(k_stream_map<9>, gr, dim3(128), 0, g->stream, g->d_inst, t, t + n, t + 2 * n);
+    else hipLaunchKernelGGL(k_stream_map<21>, gr, dim3(128), 0, g->stream, g->d_inst, t, t + n, t + 2 * n);
+    HIPCHK(g, hipGetLastError());
+    HIPCHK(g, hipMemcpyAsync(src_cell, t, n * 4, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(g, hipMemcpyAsync(src_dir, t + n, n * 4, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(g, hipMemcpyAsync(wall, t + 2 * n, n * 4, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    dfree(g, t);
+    return LBM_OK;
+}
+
+int lbm_geometry(lbm_grid *g, double *out)
+{
+    if (!g || !out) return fail(g, LBM_EINVAL, "null argument");
+    const int q = g->q, n1 = g->n1, n2 = g->n2, h = g->h, nc = g->ncell;
+    const int H1 = n1 + 2 * h, H2 = n2 + 2 * h;
+    const size_t nh = (size_t)H1 * H2;
+    const int nf = geo_fields(q);
+    double *tg = (double *)dalloc(g, nh * 4 * 8);
+    double *geo = (double *)dalloc(g, (size_t)nc * nf * 8);
+    double *jt = (double *)dalloc(g, (size_t)nc * 8);
+    double *g4t = (double *)dalloc(g, (size_t)nc * 4 * 8);
+    if (!tg || !geo || !jt || !g4t) return fail(g, LBM_ENOMEM, "allocation failed");
+    hipLaunchKernelGGL(k_tangent, dim3((H2 + 127) / 128, H1), dim3(128), 0, g->stream, g->X, g->Y, H1, H2, tg);
+    if (q == 9) hipLaunchKernelGGL(k_geom_cell<9>, cell_grid(n1, n2), dim3(128), 0, g->stream, tg, n1, n2, h, geo, jt, g4t);
+    else hipLaunchKernelGGL(k_geom_cell<21>, cell_grid(n1, n2), dim3(128), 0, g->stream, tg, n1, n2, h, geo, jt, g4t);
+    HIPCHK(g, hipGetLastError());
+    std::vector<double> hg((size_t)nc * nf);
+    HIPCHK(g, hipMemcpyAsync(hg.data(), geo, hg.size() * 8, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    dfree(g, tg);
+    dfree(g, geo);
+    dfree(g, jt);
+    dfree(g, g4t);
+    const int W = 4 + 2 * q;
+    for (int c = 0; c < nc; ++c) {
+        out[(size_t)c * W + 0] = hg[(size_t)GEO_J * nc + c];
+        out[(size_t)c * W + 1] = hg[(size_t)GEO_G11 * nc + c];
+        out[(size_t)c * W + 2] = hg[(size_t)GEO_G12 * nc + c];
+        out[(size_t)c * W + 3] = hg[(size_t)GEO_G22 * nc + c];
+        for (int k = 0; k < 2 * q; ++k) out[(size_t)c * W + 4 + k] = hg[(size_t)(GEO_A0 + k) * nc + c];
+    }
+    return LBM_OK;
+}
+
+int lbm_get_volume(lbm_grid *g, double *J)
+{
+    if (!g || !J) return fail(g, LBM_EINVAL, "null argument");
+    HIPCHK(g, hipMemcpyAsync(J, g->Jused, (size_t)g->ncell * 8, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    return LBM_OK;
+}
+
+int lbm_synchronize(lbm_grid *g)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    return LBM_OK;
+}
+
+void *lbm_stream(lbm_grid *g) { return g ? (void *)g->stream : nullptr; }
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+void lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
+    for (void *p : b->allocs) (void)hipFree(p);
+    delete b;
+}
+
+int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
+{
+    if (!grids || n <= 0 || !out) return fail(nullptr, LBM_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    lbm_batch *b = new lbm_batch();
+    b->stream = grids[0]->stream;
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    for (int k = 0; k < n; ++k) {
+        lbm_grid *g = grids[k];
+        if (!g || !g->inited) {
+            delete b;
+            return fail(nullptr, LBM_ESTATE, "every grid of a batch must be initialised");
+        }
+        if (g->stream != b->stream) {
+            delete b;
+            return fail(nullptr, LBM_EINVAL, "grids of a batch must share one stream");
+        }
+        b->grids.push_back(g);
+        groups[std::make_tuple(g->q, g->precision, g->row ? 0 : 1)].push_back(k);
+    }
+    for (auto &kv : groups) {
+        lbm_batch::Group G;
+        G.q = std::get<0>(kv.first);
+        G.precision = std::get<1>(kv.first);
+        G.cell = std::get<2>(kv.first);
+        G.wpb = b->grids[kv.second[0]]->wpb;
+        std::vector<InstDesc> descs;
+        std::vector<int4> nat;
+        for (int k : kv.second) {
+            lbm_grid *g = b->grids[k];
+            InstDesc I = g->h_inst;
+            I.par0 = g->par;
+            const int inst = (int)descs.size();
+            descs.push_back(I);
+            auto t = make_tiles(inst, g->n1, g->n2, G.wpb);
+            nat.insert(nat.end(), t.begin(), t.end());
+        }
+        // largest instances' tiles first would help tail balance; keep the
+        // natural order (instances contiguous) so each XCD works on few grids
+        auto ord = xcd_order(nat, 1 << 30);
+        void *di = nullptr, *dt = nullptr;
+        if (hipMalloc(&di, descs.size() * sizeof(InstDesc)) != hipSuccess ||
+            hipMalloc(&dt, ord.size() * sizeof(int4)) != hipSuccess) {
+            lbm_batch_destroy(b);
+            return fail(nullptr, LBM_ENOMEM, "batch allocation failed");
+        }
+        b->allocs.push_back(di);
+        b->allocs.push_back(dt);
+        if (hipMemcpy(di, descs.data(), descs.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(dt, ord.data(), ord.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) {
+            lbm_batch_destroy(b);
+            return fail(nullptr, LBM_EDEVICE, "batch upload failed");
+        }
+        G.d_inst = (InstDesc *)di;
+        G.d_tiles = (int4 *)dt;
+        G.ntiles = (int)ord.size();
+        b->groups.push_back(G);
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+static int batch_launch(lbm_batch *b, int par)
+{
+    for (auto &G : b->groups) {
+        StepFn fn = pick_step(G.q, G.precision, G.cell, 0);
+        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), 0, b->stream, (const InstDesc *)G.d_inst,
+                           (const int4 *)G.d_tiles, par);
+    }
+    if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "batch step launch failed");
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int64_t n)
+{
+    if (!b || n < 0) return fail(nullptr, LBM_EINVAL, "bad batch step arguments");
+    const int GS = 16;
+    int64_t left = n;
+    // the batch's own parity: step s of the batch uses par = s & 1
+    if (left >= GS && (b->step & 1) == 0) {
+        if (!b->graph.exec) {
+            hipGraph_t graph = nullptr;
+            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return fail(nullptr, LBM_EDEVICE, "capture failed");
+            for (int s = 0; s < GS; ++s) batch_launch(b, s & 1);
+            if (hipStreamEndCapture(b->stream, &graph) != hipSuccess ||
+                hipGraphInstantiate(&b->graph.exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                return fail(nullptr, LBM_EDEVICE, "graph instantiation failed");
+            (void)hipGraphDestroy(graph);
+            b->graph.steps = GS;
+        }
+        while (left >= GS) {
+            if (hipGraphLaunch(b->graph.exec, b->stream) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "graph launch failed");
+            left -= GS;
+            b->step += GS;
+        }
+    }
+    for (; left > 0; --left) {
+        int rc = batch_launch(b, (int)(b->step & 1));
+        if (rc != LBM_OK) return rc;
+        b->step += 1;
+    }
+    for (lbm_grid *g : b->grids) {
+        g->par ^= (int)(n & 1);
+        g->step += n;
+    }
+    return LBM_OK;
+}
+
+int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream)
+{
+    if (!dst || !src || (bytes & 15)) return fail(nullptr, LBM_EINVAL, "copy probe needs 16-byte multiples");
+    hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, (hipStream_t)stream, (const uint4 *)src, (uint4 *)dst,
+                       bytes / 16);
+    if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "copy probe launch failed");
+    return LBM_OK;
+}
+
+} // extern "C"

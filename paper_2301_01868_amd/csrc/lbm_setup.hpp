@@ -1,0 +1,428 @@
+// Device code for grid set-up, state transfer and reductions (FP64).
+//
+// Geometry (arXiv:2301.01868, Sec. 2): tangent basis by central differences of
+// the mapping (Eqs. distance, tangent), volume J = (g_1 x g_2).z (Eq. metric),
+// co-tangents g^1 = (g_2 x z)/J, g^2 = (z x g_1)/J and g^ij = g^i . g^j
+// (Eq. covectors), and the Christoffel sums of Eq. (gamma) folded with the
+// lattice vectors: A+^i_a(q) = g^i(q) . [e_a(q + c_a) - e_a(q)] with
+// e_a = c^j_a g_j (Eq. lattice).
+#pragma once
+
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+// per-cell FP64 geometry fields (struct of arrays, [field][cell])
+enum { GEO_J = 0, GEO_G11, GEO_G12, GEO_G22, GEO_G1X, GEO_G1Y, GEO_G2X, GEO_G2Y, GEO_A0 };
+__host__ __device__ constexpr int geo_fields(int Q) { return GEO_A0 + 2 * Q; }
+
+// tangent vectors on the halo range (one layer less than the mapping)
+__global__ void k_tangent(const double *__restrict__ X, const double *__restrict__ Y, int H1, int H2,
+                          double *__restrict__ tg)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y;
+    if (b >= H2 || a >= H1) return;
+    const size_t k = (size_t)a * H2 + b, n = (size_t)H1 * H2;
+    if (a == 0 || b == 0 || a == H1 - 1 || b == H2 - 1) {
+        tg[k] = tg[n + k] = tg[2 * n + k] = tg[3 * n + k] = __builtin_nan("");
+        return;
+    }
+    tg[k] = 0.5 * (X[k + H2] - X[k - H2]);
+    tg[n + k] = 0.5 * (Y[k + H2] - Y[k - H2]);
+    tg[2 * n + k] = 0.5 * (X[k + 1] - X[k - 1]);
+    tg[3 * n + k] = 0.5 * (Y[k + 1] - Y[k - 1]);
+}
+
+template <int Q>
+__global__ void k_geom_cell(const double *__restrict__ tg, int n1, int n2, int h, double *__restrict__ geo,
+                            double *__restrict__ Jgeo, double *__restrict__ g4)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n2 || i >= n1) return;
+    const int H2 = n2 + 2 * h;
+    const size_t nh = (size_t)(n1 + 2 * h) * H2;
+    const size_t nc = (size_t)n1 * n2;
+    const size_t c = (size_t)i * n2 + j;
+    auto at = [&](int di, int dj, int f) { return tg[f * nh + (size_t)(i + h + di) * H2 + (j + h + dj)]; };
+    const double g1x = at(0, 0, 0), g1y = at(0, 0, 1), g2x = at(0, 0, 2), g2y = at(0, 0, 3);
+    const double J = g1x * g2y - g1y * g2x;
+    const double u1x = g2y / J, u1y = -g2x / J;   // g^1
+    const double u2x = -g1y / J, u2y = g1x / J;   // g^2
+    geo[GEO_J * nc + c] = J;
+    geo[GEO_G11 * nc + c] = u1x * u1x + u1y * u1y;
+    geo[GEO_G12 * nc + c] = u1x * u2x + u1y * u2y;
+    geo[GEO_G22 * nc + c] = u2x * u2x + u2y * u2y;
+    geo[GEO_G1X * nc + c] = g1x;
+    geo[GEO_G1Y * nc + c] = g1y;
+    geo[GEO_G2X * nc + c] = g2x;
+    geo[GEO_G2Y * nc + c] = g2y;
+    Jgeo[c] = J;
+    g4[c] = g1x;
+    g4[nc + c] = g1y;
+    g4[2 * nc + c] = g2x;
+    g4[3 * nc + c] = g2y;
+    for (int a = 0; a < Q; ++a) {
+        const int c1 = cx(a), c2 = cy(a);
+        const double ex0 = c1 * g1x + c2 * g2x, ey0 = c1 * g1y + c2 * g2y;
+        const double ex1 = c1 * at(c1, c2, 0) + c2 * at(c1, c2, 2);
+        const double ey1 = c1 * at(c1, c2, 1) + c2 * at(c1, c2, 3);
+        const double dx = ex1 - ex0, dy = ey1 - ey0;
+        geo[(GEO_A0 + 2 * a) * nc + c] = (a == 0) ? 0.0 : u1x * dx + u1y * dy;
+        geo[(GEO_A0 + 2 * a + 1) * nc + c] = (a == 0) ? 0.0 : u2x * dx + u2y * dy;
+    }
+}
+
+// row invariance: does any rotation-invariant field (J, g^ij, A+) of cell
+// (i, j) differ from cell (i, 0)?  Also flags non-positive J.
+__global__ void k_rowcheck(const double *__restrict__ geo, int n1, int n2, int nf, double tol, int *__restrict__ flag)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n2 || i >= n1) return;
+    const size_t nc = (size_t)n1 * n2;
+    const size_t c = (size_t)i * n2 + j, c0 = (size_t)i * n2;
+    if (!(geo[GEO_J * nc + c] > 0.0)) flag[1] = 1;
+    for (int f = 0; f < nf; ++f) {
+        if (f >= GEO_G1X && f < GEO_A0) continue;   // the basis vectors themselves may rotate
+        const double v = geo[f * nc + c], v0 = geo[f * nc + c0];
+        if (!(fabs(v - v0) <= tol * (1.0 + fabs(v0)))) {
+            flag[0] = 1;
+            return;
+        }
+    }
+}
+
+// Row-table grids: give every cell of a row the row's (column 0) volume and
+// inverse metric, so that a state that does not depend on q2 stays exactly
+// (bitwise) independent of q2.
+__global__ void k_canon_rows(int n1, int n2, double *__restrict__ J, double *__restrict__ G3)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n2 || i >= n1 || j == 0) return;
+    const size_t nc = (size_t)n1 * n2, c = (size_t)i * n2 + j, c0 = (size_t)i * n2;
+    J[c] = J[c0];
+    G3[c] = G3[c0];
+    G3[nc + c] = G3[nc + c0];
+    G3[2 * nc + c] = G3[2 * nc + c0];
+}
+
+// ---------------------------------------------------------------------------
+// table building.  An "entry" is a row (row tables) or a cell (cell tables);
+// the geometry of entry e is taken at cell ecell(e).
+// ---------------------------------------------------------------------------
+struct TableArgs {
+    const double *geo;   // [field][ncell]
+    int n1, n2, ncell, cellmode, nent;
+    int periodic1, bc_lo, bc_hi, base_kind;
+    double rho0;
+};
+
+__host__ __device__ inline int entry_cell(const TableArgs &t, int e) { return t.cellmode ? e : e * t.n2; }
+
+template <int Q>
+__device__ inline double rest_phi(int a, double G11, double G12, double G22)
+{
+    constexpr double T0 = lattice_T0<Q>();
+    const double c1 = cx(a), c2 = cy(a);
+    const double cGc = c1 * c1 * G11 + 2.0 * c1 * c2 * G12 + c2 * c2 * G22;
+    return weight<Q>(a) * (1.0 + (cGc - (c1 * c1 + c2 * c2) - T0 * (G11 + G22 - 2.0)) / (2.0 * T0));
+}
+
+// base B_a per entry (FP64) and its sum
+template <int Q>
+__global__ void k_base(TableArgs t, double *__restrict__ base, double *__restrict__ mB64)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= t.nent) return;
+    const size_t nc = (size_t)t.ncell;
+    const int c = entry_cell(t, e);
+    const double J = t.geo[GEO_J * nc + c];
+    const double G11 = t.geo[GEO_G11 * nc + c], G12 = t.geo[GEO_G12 * nc + c], G22 = t.geo[GEO_G22 * nc + c];
+    double s = 0.0;
+    for (int a = 0; a < Q; ++a) {
+        double B = 0.0;
+        if (t.base_kind == 0) B = J * t.rho0 * rest_phi<Q>(a, G11, G12, G22);
+        else if (t.base_kind == 1) B = J * t.rho0 * weight<Q>(a);
+        base[(size_t)e * Q + a] = B;
+        s += B;
+    }
+    mB64[e] = s;
+}
+
+template <int Q, typename T>
+__global__ void k_table(TableArgs t, const double *__restrict__ base, const double *__restrict__ mB64,
+                        T *__restrict__ tab)
+{
+    using TB = Tab<Q>;
+    constexpr double T0 = lattice_T0<Q>();
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= t.nent) return;
+    const size_t nc = (size_t)t.ncell;
+    const int c = entry_cell(t, e);
+    const int i = c / t.n2, j = c % t.n2;
+    auto put = [&](int f, double v) {
+        if (t.cellmode) tab[(size_t)f * t.nent + e] = (T)v;
+        else tab[(size_t)e * TB::STRIDE + f] = (T)v;
+    };
+    const double G11 = t.geo[GEO_G11 * nc + c], G12 = t.geo[GEO_G12 * nc + c], G22 = t.geo[GEO_G22 * nc + c];
+    auto A = [&](int a, int comp) { return t.geo[(GEO_A0 + 2 * a + comp) * nc + c]; };
+    const double *B = base + (size_t)e * Q;
+    const double mB = mB64[e];
+    put(TB::G11, G11);
+    put(TB::G12, G12);
+    put(TB::G22, G22);
+    put(TB::MB, mB);
+    double C1 = 0.0, C2 = 0.0;
+    for (int a = 1; a < Q; ++a) {
+        C1 += (A(a, 0) + A(opp(a), 0)) * B[a];
+        C2 += (A(a, 1) + A(opp(a), 1)) * B[a];
+    }
+    put(TB::C1, C1);
+    put(TB::C2, C2);
+    auto phiB = [&](int a) { return mB != 0.0 ? B[a] / mB : 0.0; };
+    put(TB::D0, rest_phi<Q>(0, G11, G12, G22) - phiB(0));
+    put(TB::PHIB0, phiB(0));
+    for (int a = 1; a < Q; ++a) {
+        put(TB::A1(a), A(a, 0));
+        put(TB::A2(a), A(a, 1));
+        // base of the pulled source relative to this entry's base
+        int r, beta, wall;
+        pull_source(i, a, t.n1, t.periodic1, t.bc_lo, t.bc_hi, r, beta, wall);
+        int se = r;
+        if (t.cellmode) {
+            int sj = j - cy(a);
+            sj = ((sj % t.n2) + t.n2) % t.n2;
+            se = r * t.n2 + sj;
+        }
+        put(TB::DB(a), base[(size_t)se * Q + beta] - B[a]);
+    }
+    for (int p = 0; p < npair<Q>(); ++p) {
+        const int a = pair_rep(p);
+        const double c1 = cx(a), c2 = cy(a);
+        const double cGc = c1 * c1 * G11 + 2.0 * c1 * c2 * G12 + c2 * c2 * G22;
+        put(TB::K(p), weight<Q>(a) * (cGc - T0 * (G11 + G22)) / (2.0 * T0 * T0));
+        put(TB::D(p), rest_phi<Q>(a, G11, G12, G22) - phiB(a));
+        put(TB::PHIB(p), phiB(a));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initial state N = J f^eq(rho0, U = Ut = u0; g^ij), FP64 closed form
+// ---------------------------------------------------------------------------
+template <int Q>
+__device__ inline double feq_phi(int a, const double U[2], const double Ut[2], double G11, double G12, double G22)
+{
+    constexpr double T0 = lattice_T0<Q>();
+    const double c1 = cx(a), c2 = cy(a), w = weight<Q>(a);
+    const double cc = c1 * c1 + c2 * c2;
+    const double cU = c1 * U[0] + c2 * U[1];
+    const double cUt = c1 * Ut[0] + c2 * Ut[1];
+    const double GU1 = G11 * Ut[0] + G12 * Ut[1], GU2 = G12 * Ut[0] + G22 * Ut[1];
+    const double cGU = c1 * GU1 + c2 * GU2;
+    const double uu = Ut[0] * Ut[0] + Ut[1] * Ut[1];
+    const double cGc = c1 * c1 * G11 + 2.0 * c1 * c2 * G12 + c2 * c2 * G22;
+    const double K = w * (cGc - T0 * (G11 + G22)) / (2.0 * T0 * T0);
+    const double even = rest_phi<Q>(a, G11, G12, G22) + w * (cUt * cUt / T0 - uu) / (2.0 * T0);
+    const double odd = w * (cU * (1.0 / T0 + (4.0 * T0 - cc) / (2.0 * T0 * T0)) - cGU / T0 +
+                            (cUt * cUt - 3.0 * T0 * uu) * cUt / (6.0 * T0 * T0 * T0)) +
+                       K * cUt;
+    return even + odd;
+}
+
+struct InitArgs {
+    const double *G3;     // [3][ncell] inverse metric
+    const double *Jused;  // [ncell]
+    const double *u0;     // [ncell][2] or null
+    const double *base;   // [nent][Q]
+    double rho0;
+    int cellmode;
+    int pin;
+};
+
+template <int Q, typename T, typename S>
+__global__ void k_init(const InstDesc *__restrict__ dd, InitArgs ia)
+{
+    const InstDesc *d = dd;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= d->n2 || i >= d->n1) return;
+    const size_t nc = (size_t)d->ncell;
+    const int c = i * d->n2 + j;
+    const int e = ia.cellmode ? c : i;
+    const double m = ia.Jused[c] * ia.rho0;
+    double U[2] = {0.0, 0.0};
+    if (ia.u0) {
+        U[0] = ia.u0[2 * (size_t)c];
+        U[1] = ia.u0[2 * (size_t)c + 1];
+    }
+    const double G11 = ia.G3[c], G12 = ia.G3[nc + c], G22 = ia.G3[2 * nc + c];
+    S *P = (S *)d->P[ia.pin];
+    for (int a = 0; a < Q; ++a) {
+        const double N = m * feq_phi<Q>(a, U, U, G11, G12, G22);
+        P[(size_t)a * d->plane + (size_t)i * d->pitch + j] = (S)(N - ia.base[(size_t)e * Q + a]);
+    }
+    T *side = (T *)d->side[ia.pin];
+    const int hw = d->hw;
+    if (d->bc_lo == BC_MOVING && i < hw) {
+        side[((size_t)0 * hw + i) * d->pitch + j] = (T)m;
+        side[((size_t)1 * hw + i) * d->pitch + j] = (T)U[1];
+    }
+    if (d->bc_hi == BC_MOVING && i >= d->n1 - hw) {
+        const int k = d->n1 - 1 - i;
+        side[((size_t)2 * hw + k) * d->pitch + j] = (T)m;
+        side[((size_t)3 * hw + k) * d->pitch + j] = (T)U[1];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// state transfer: absolute FP64 particle numbers <-> stored offsets
+// ---------------------------------------------------------------------------
+template <int Q, typename S>
+__global__ void k_state_out(const InstDesc *__restrict__ d, const double *__restrict__ base, int cellmode, int pin,
+                            double *__restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= d->n2 || i >= d->n1) return;
+    const int c = i * d->n2 + j, e = cellmode ? c : i;
+    const S *P = (const S *)d->P[pin];
+    for (int a = 0; a < Q; ++a)
+        out[(size_t)a * d->ncell + c] = base[(size_t)e * Q + a] + (double)P[(size_t)a * d->plane + (size_t)i * d->pitch + j];
+}
+
+template <int Q, typename S>
+__global__ void k_state_in(const InstDesc *__restrict__ d, const double *__restrict__ base, int cellmode, int pin,
+                           const double *__restrict__ in)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= d->n2 || i >= d->n1) return;
+    const int c = i * d->n2 + j, e = cellmode ? c : i;
+    S *P = (S *)d->P[pin];
+    for (int a = 0; a < Q; ++a)
+        P[(size_t)a * d->plane + (size_t)i * d->pitch + j] = (S)(in[(size_t)a * d->ncell + c] - base[(size_t)e * Q + a]);
+}
+
+// side state [2][2][hw][pitch] (compute type) <-> [2][2][hw][n2] FP64
+template <typename T>
+__global__ void k_side_io(const InstDesc *__restrict__ d, int pin, double *__restrict__ host_layout, int to_device)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;   // 0 .. 4*hw-1
+    if (j >= d->n2 || k >= 4 * d->hw) return;
+    T *side = (T *)d->side[pin];
+    if (to_device) side[(size_t)k * d->pitch + j] = (T)host_layout[(size_t)k * d->n2 + j];
+    else host_layout[(size_t)k * d->n2 + j] = (double)side[(size_t)k * d->pitch + j];
+}
+
+// the streaming map as the step kernel uses it
+template <int Q>
+__global__ void k_stream_map(const InstDesc *__restrict__ d, int *__restrict__ sc, int *__restrict__ sd,
+                             int *__restrict__ wl)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const int n1 = d->n1, n2 = d->n2;
+    if (j >= n2 || i >= n1) return;
+    constexpr int CM = cmax<Q>();
+    int col[2 * CM + 1];
+    for (int k = -CM; k <= CM; ++k) col[k + CM] = (n2 >= CM) ? wrap_col(j - k, n2) : ((j - k) % n2 + n2) % n2;
+    for (int a = 0; a < Q; ++a) {
+        int r, beta, wall;
+        pull_source(i, a, n1, d->periodic1, d->bc_lo, d->bc_hi, r, beta, wall);
+        const size_t k = ((size_t)i * n2 + j) * Q + a;
+        sc[k] = r * n2 + col[cy(a) + CM];
+        sd[k] = beta;
+        wl[k] = wall;
+    }
+}
+
+// J' = m / rho0
+__global__ void k_volume_from_mass(const double *__restrict__ m, double rho0, int n, double *__restrict__ J)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) J[c] = m[c] / rho0;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions with wavefront shuffles; fixed grid, fixed order
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 512;
+constexpr int RED_THREADS = 256;
+constexpr int RED_NF = 6;   // mass, |d mUt|^2, |mUt|^2, KE, AM, bad
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+struct ReduceArgs {
+    const double *mom;   // [5][n]
+    double *snap;        // [2][n]
+    const double *g4;    // [4][n]
+    const double *xc, *yc;
+    int n;
+    int update_snap;
+    double *partial;     // [RED_BLOCKS][RED_NF]
+};
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce(ReduceArgs r)
+{
+    double acc[RED_NF] = {0, 0, 0, 0, 0, 0};
+    const size_t n = (size_t)r.n;
+    for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < n; c += (size_t)RED_BLOCKS * RED_THREADS) {
+        const double m = r.mom[c], Ut1 = r.mom[3 * n + c], Ut2 = r.mom[4 * n + c];
+        const double p1 = m * Ut1, p2 = m * Ut2;
+        const double s1 = r.snap[c], s2 = r.snap[n + c];
+        if (r.update_snap) {
+            r.snap[c] = p1;
+            r.snap[n + c] = p2;
+        }
+        const double g1x = r.g4[c], g1y = r.g4[n + c], g2x = r.g4[2 * n + c], g2y = r.g4[3 * n + c];
+        const double ux = Ut1 * g1x + Ut2 * g2x, uy = Ut1 * g1y + Ut2 * g2y;
+        const bool bad = !(m > 0.0) || !isfinite(m) || !isfinite(Ut1) || !isfinite(Ut2);
+        acc[0] += m;
+        acc[1] += (p1 - s1) * (p1 - s1) + (p2 - s2) * (p2 - s2);
+        acc[2] += p1 * p1 + p2 * p2;
+        acc[3] += 0.5 * m * (ux * ux + uy * uy);
+        acc[4] += m * (r.xc[c] * uy - r.yc[c] * ux);
+        acc[5] += bad ? 1.0 : 0.0;
+    }
+    __shared__ double sh[RED_THREADS / 64][RED_NF];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+    for (int f = 0; f < RED_NF; ++f) {
+        const double v = wave_sum(acc[f]);
+        if (ln == 0) sh[wv][f] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < RED_NF) {
+        double v = 0.0;
+        for (int w = 0; w < RED_THREADS / 64; ++w) v += sh[w][threadIdx.x];
+        r.partial[(size_t)blockIdx.x * RED_NF + threadIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_reduce_final(const double *__restrict__ partial, double *__restrict__ out)
+{
+    // one wave: lane l sums blocks l, l+64, ... per field, then a shuffle tree
+    for (int f = 0; f < RED_NF; ++f) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < RED_BLOCKS; b += 64) v += partial[(size_t)b * RED_NF + f];
+        v = wave_sum(v);
+        if (threadIdx.x == 0) out[f] = v;
+    }
+}
+
+__global__ void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n16)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
+} // namespace lbm

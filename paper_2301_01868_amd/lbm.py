@@ -1,0 +1,334 @@
+"""Thin ctypes binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every function has the ABI's name and forwards to ``liblbm.so``; nothing here
+computes any step of the method.  Loading fails loudly when the library has
+not been built (``python -m paper_2301_01868_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_PERIODIC, LBM_NOSLIP, LBM_MOVING = 0, 1, 2
+LBM_FP64, LBM_FP32 = 0, 1
+LBM_BASE_LOCAL_REST, LBM_BASE_W_RHO0, LBM_BASE_NONE = 0, 1, 2
+LBM_GEOM_AUTO, LBM_GEOM_CELL = 0, 1
+BC = {"periodic": LBM_PERIODIC, "noslip": LBM_NOSLIP, "moving": LBM_MOVING}
+
+EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_error", "lbm_grid_info_get",
+            "lbm_set_volume", "lbm_get_volume", "lbm_init", "lbm_step", "lbm_moments", "lbm_residual", "lbm_noflow_adjust",
+            "lbm_get_state", "lbm_set_state", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
+            "lbm_stream", "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_set_launch",
+            "lbm_copy_probe"]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("lbm error %d: %s" % (code, msg))
+        self.code = code
+
+
+class lbm_allocator(ct.Structure):
+    _fields_ = [("alloc", ct.c_void_p), ("free", ct.c_void_p), ("ctx", ct.c_void_p)]
+
+
+class lbm_grid_desc(ct.Structure):
+    _fields_ = [("q", ct.c_int32), ("n1", ct.c_int32), ("n2", ct.c_int32), ("halo", ct.c_int32),
+                ("x", ct.POINTER(ct.c_double)), ("y", ct.POINTER(ct.c_double)),
+                ("bc_lo", ct.c_int32), ("bc_hi", ct.c_int32), ("ut_lo", ct.c_double), ("ut_hi", ct.c_double),
+                ("tau", ct.c_double), ("accel", ct.c_double * 2), ("rho0", ct.c_double),
+                ("precision", ct.c_int32), ("offset_base", ct.c_int32), ("iterations", ct.c_int32),
+                ("geometry", ct.c_int32), ("alloc", ct.POINTER(lbm_allocator)), ("stream", ct.c_void_p)]
+
+
+class lbm_resid(ct.Structure):
+    _fields_ = [("step", ct.c_int64), ("residual", ct.c_double), ("mass", ct.c_double),
+                ("mass_rel_drift", ct.c_double), ("kinetic_energy", ct.c_double),
+                ("angular_momentum", ct.c_double), ("bad_cells", ct.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class lbm_grid_info(ct.Structure):
+    _fields_ = [("q", ct.c_int32), ("n1", ct.c_int32), ("n2", ct.c_int32), ("pitch", ct.c_int32),
+                ("precision", ct.c_int32), ("row_tables", ct.c_int32), ("step", ct.c_int64),
+                ("bytes_per_update", ct.c_double), ("device_bytes", ct.c_size_t)]
+
+
+_lib = None
+
+
+def load():
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("HIP library not built: %s (run python -m paper_2301_01868_amd.build)" % LIB_PATH)
+    L = ct.CDLL(LIB_PATH)
+    D = ct.POINTER(ct.c_double)
+    I32 = ct.POINTER(ct.c_int32)
+    vp = ct.c_void_p
+    L.lbm_lattice.argtypes = [ct.c_int32, I32, I32, D, D]
+    L.lbm_grid_create.argtypes = [ct.POINTER(lbm_grid_desc), ct.POINTER(vp)]
+    L.lbm_grid_destroy.argtypes = [vp]
+    L.lbm_grid_destroy.restype = None
+    L.lbm_last_error.argtypes = [vp]
+    L.lbm_last_error.restype = ct.c_char_p
+    L.lbm_grid_info_get.argtypes = [vp, ct.POINTER(lbm_grid_info)]
+    L.lbm_set_volume.argtypes = [vp, D]
+    L.lbm_init.argtypes = [vp, D]
+    L.lbm_get_volume.argtypes = [vp, D]
+    L.lbm_step.argtypes = [vp, ct.c_int64]
+    L.lbm_moments.argtypes = [vp, D, D, D]
+    L.lbm_residual.argtypes = [vp, ct.POINTER(lbm_resid)]
+    L.lbm_noflow_adjust.argtypes = [vp, ct.c_double, ct.c_int64, ct.c_int32, ct.POINTER(ct.c_int64)]
+    L.lbm_get_state.argtypes = [vp, D, D]
+    L.lbm_set_state.argtypes = [vp, D, D]
+    L.lbm_stream_map.argtypes = [vp, I32, I32, I32]
+    L.lbm_geometry.argtypes = [vp, D]
+    L.lbm_synchronize.argtypes = [vp]
+    L.lbm_stream.argtypes = [vp]
+    L.lbm_stream.restype = vp
+    L.lbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int32, ct.POINTER(vp)]
+    L.lbm_batch_step.argtypes = [vp, ct.c_int64]
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_destroy.restype = None
+    L.lbm_set_launch.argtypes = [vp, ct.c_int32]
+    L.lbm_copy_probe.argtypes = [vp, vp, ct.c_size_t, vp]
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _chk(rc, handle=None):
+    if rc != LBM_OK:
+        raise LbmError(rc, load().lbm_last_error(handle).decode(errors="replace"))
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# functions with the ABI's names
+# ---------------------------------------------------------------------------
+def lbm_lattice(q):
+    cx = (ct.c_int32 * q)()
+    cy = (ct.c_int32 * q)()
+    w = np.zeros(q)
+    T0 = ct.c_double()
+    _chk(load().lbm_lattice(q, cx, cy, _dp(w), ct.byref(T0)))
+    return np.stack([np.array(cx[:]), np.array(cy[:])], 1), w, T0.value
+
+
+def lbm_grid_create(case, precision=LBM_FP64, offset_base=LBM_BASE_LOCAL_REST, iterations=0,
+                    geometry=LBM_GEOM_AUTO, stream=None):
+    """Create a grid from a grids.Case (mapping + boundary + parameters)."""
+    X = np.ascontiguousarray(case.X, dtype=np.float64)
+    Y = np.ascontiguousarray(case.Y, dtype=np.float64)
+    d = lbm_grid_desc()
+    d.q, d.n1, d.n2, d.halo = case.q, case.n1, case.n2, case.halo
+    d.x, d.y = _dp(X), _dp(Y)
+    d.bc_lo, d.bc_hi = BC[case.bc_lo], BC[case.bc_hi]
+    if case.periodic1:
+        d.bc_lo = d.bc_hi = LBM_PERIODIC
+    d.ut_lo, d.ut_hi = float(case.ut_lo), float(case.ut_hi)
+    d.tau = float(case.tau)
+    d.accel[0], d.accel[1] = float(case.accel[0]), float(case.accel[1])
+    d.rho0 = float(case.rho0)
+    d.precision, d.offset_base, d.iterations, d.geometry = precision, offset_base, iterations, geometry
+    d.alloc = None
+    d.stream = stream
+    h = ct.c_void_p()
+    _chk(load().lbm_grid_create(ct.byref(d), ct.byref(h)))
+    return h
+
+
+def lbm_grid_destroy(h):
+    load().lbm_grid_destroy(h)
+
+
+def lbm_grid_info_get(h):
+    info = lbm_grid_info()
+    _chk(load().lbm_grid_info_get(h, ct.byref(info)), h)
+    return info
+
+
+def lbm_set_volume(h, J=None):
+    J = None if J is None else np.ascontiguousarray(J, dtype=np.float64)
+    _chk(load().lbm_set_volume(h, _dp(J)), h)
+
+
+def lbm_get_volume(h, ncell):
+    J = np.zeros(ncell)
+    _chk(load().lbm_get_volume(h, _dp(J)), h)
+    return J
+
+
+def lbm_init(h, u0=None):
+    u0 = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64)
+    _chk(load().lbm_init(h, _dp(u0)), h)
+
+
+def lbm_step(h, n):
+    _chk(load().lbm_step(h, int(n)), h)
+
+
+def lbm_moments(h, ncell):
+    m = np.zeros(ncell)
+    U = np.zeros((ncell, 2))
+    Ut = np.zeros((ncell, 2))
+    _chk(load().lbm_moments(h, _dp(m), _dp(U), _dp(Ut)), h)
+    return m, U, Ut
+
+
+def lbm_residual(h, check=True):
+    r = lbm_resid()
+    rc = load().lbm_residual(h, ct.byref(r))
+    if check:
+        _chk(rc, h)
+    return r
+
+
+def lbm_noflow_adjust(h, tol=1e-12, max_steps=10 ** 7, check_every=1000):
+    steps = ct.c_int64()
+    _chk(load().lbm_noflow_adjust(h, float(tol), int(max_steps), int(check_every), ct.byref(steps)), h)
+    return steps.value
+
+
+def lbm_get_state(h, q, n1, n2, cmax):
+    P = np.zeros((q, n1, n2))
+    side = np.zeros((2, 2, cmax, n2))
+    _chk(load().lbm_get_state(h, _dp(P), _dp(side)), h)
+    return P, side
+
+
+def lbm_set_state(h, P=None, side=None):
+    P = None if P is None else np.ascontiguousarray(P, dtype=np.float64)
+    side = None if side is None else np.ascontiguousarray(side, dtype=np.float64)
+    _chk(load().lbm_set_state(h, _dp(P), _dp(side)), h)
+
+
+def lbm_stream_map(h, ncell, q):
+    sc = np.zeros((ncell, q), np.int32)
+    sd = np.zeros((ncell, q), np.int32)
+    wl = np.zeros((ncell, q), np.int32)
+    I32 = ct.POINTER(ct.c_int32)
+    _chk(load().lbm_stream_map(h, sc.ctypes.data_as(I32), sd.ctypes.data_as(I32), wl.ctypes.data_as(I32)), h)
+    return sc, sd, wl
+
+
+def lbm_geometry(h, ncell, q):
+    out = np.zeros((ncell, 4 + 2 * q))
+    _chk(load().lbm_geometry(h, _dp(out)), h)
+    return out
+
+
+def lbm_synchronize(h):
+    _chk(load().lbm_synchronize(h), h)
+
+
+def lbm_stream(h):
+    return load().lbm_stream(h)
+
+
+def lbm_set_launch(h, waves_per_block):
+    _chk(load().lbm_set_launch(h, int(waves_per_block)), h)
+
+
+def lbm_batch_create(handles):
+    arr = (ct.c_void_p * len(handles))(*[h.value if isinstance(h, ct.c_void_p) else h for h in handles])
+    b = ct.c_void_p()
+    _chk(load().lbm_batch_create(arr, len(handles), ct.byref(b)))
+    return b
+
+
+def lbm_batch_step(b, n):
+    _chk(load().lbm_batch_step(b, int(n)))
+
+
+def lbm_batch_destroy(b):
+    load().lbm_batch_destroy(b)
+
+
+def lbm_copy_probe(dst_ptr, src_ptr, nbytes, stream=None):
+    _chk(load().lbm_copy_probe(ct.c_void_p(dst_ptr), ct.c_void_p(src_ptr), int(nbytes), stream))
+
+
+# ---------------------------------------------------------------------------
+# a small object wrapper over the same calls
+# ---------------------------------------------------------------------------
+class Grid:
+    def __init__(self, case, precision=LBM_FP64, offset_base=LBM_BASE_LOCAL_REST, iterations=0,
+                 geometry=LBM_GEOM_AUTO, stream=None):
+        self.case = case
+        self.q, self.n1, self.n2 = case.q, case.n1, case.n2
+        self.ncell = case.n1 * case.n2
+        self.cmax = 1 if case.q == 9 else 3
+        self.h = lbm_grid_create(case, precision, offset_base, iterations, geometry, stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbm_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self):
+        return lbm_grid_info_get(self.h)
+
+    def set_volume(self, J=None):
+        lbm_set_volume(self.h, J)
+
+    def get_volume(self):
+        return lbm_get_volume(self.h, self.ncell)
+
+    def init(self, u0=None):
+        lbm_init(self.h, u0)
+
+    def step(self, n=1):
+        lbm_step(self.h, n)
+
+    def moments(self):
+        return lbm_moments(self.h, self.ncell)
+
+    def residual(self, check=True):
+        return lbm_residual(self.h, check)
+
+    def noflow_adjust(self, tol=1e-12, max_steps=10 ** 7, check_every=1000):
+        return lbm_noflow_adjust(self.h, tol, max_steps, check_every)
+
+    def get_state(self):
+        return lbm_get_state(self.h, self.q, self.n1, self.n2, self.cmax)
+
+    def set_state(self, P=None, side=None):
+        lbm_set_state(self.h, P, side)
+
+    def stream_map(self):
+        return lbm_stream_map(self.h, self.ncell, self.q)
+
+    def geometry(self):
+        return lbm_geometry(self.h, self.ncell, self.q)
+
+    def synchronize(self):
+        lbm_synchronize(self.h)
+
+    def set_launch(self, wpb):
+        lbm_set_launch(self.h, wpb)
+
+    @property
+    def stream(self):
+        return lbm_stream(self.h)

@@ -1,0 +1,107 @@
+"""Full-size workloads on the GPU checked against the oracle (needs an MI355X).
+
+At full size the oracle cannot afford whole trajectories, so each check uses
+what it can compute: one step from the GPU's own state on sampled cells, the
+exact theta-reduction of the annulus (one theta column continued with the true
+angular step), and invariants (mass, theta-invariance)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import norm_rel, say, side_to_oracle, to_oracle_state
+from paper_2301_01868_amd import grids as G
+from paper_2301_01868_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _one_step_sampled(g, case, nsample=1500, seed=0):
+    P0, side0 = g.get_state()
+    o = oracle.OracleGrid(case)
+    o.set_state(to_oracle_state(P0))
+    m_s, u_s = side_to_oracle(side0, case.n1, case.n2)
+    o.set_side(np.nan_to_num(m_s), np.nan_to_num(u_s))
+    rng = np.random.default_rng(seed)
+    # every wall-adjacent row plus random interior cells
+    rows = list(range(min(4, case.n1))) + list(range(max(0, case.n1 - 4), case.n1))
+    cells = [r * case.n2 + int(rng.integers(case.n2)) for r in rows]
+    cells += list(rng.choice(case.ncell, nsample, replace=False))
+    cells = np.array(sorted(set(cells)), dtype=np.int32)
+    ref = o.step_cells(cells)
+    g.step(1)
+    P1, _ = g.get_state()
+    got = to_oracle_state(P1)[cells]
+    return np.abs(got - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec,steps,tol1,tolu", [(lbm.LBM_FP32, 2000, 3e-6, 1e-5), (lbm.LBM_FP64, 600, 1e-13, 1e-12)],
+                         ids=["fp32", "fp64"])
+def test_annulus_256x1024(prec, steps, tol1, tolu):
+    case = G.workload_annulus_couette(256, 1024, tau=0.8)
+    say("annulus 256x1024 q21 prec", prec, "steps", steps)
+    g = lbm.Grid(case, precision=prec)
+    assert g.info.row_tables == 1
+    g.init()
+    r0 = g.residual()
+    g.step(steps)
+    r = g.residual()
+    assert r.bad_cells == 0
+    assert abs(r.mass - r0.mass) / r0.mass < (2e-6 if prec == lbm.LBM_FP32 else 1e-13)
+    P, _ = g.get_state()
+    # row tables shared by all columns keep a theta-invariant state exactly invariant
+    assert (P == P[:, :, :1]).all()
+    # exact theta-reduction on the oracle
+    red = oracle.OracleGrid(G.workload_annulus_couette(256, 1024, tau=0.8, n2=1))
+    red.init(1.0)
+    red.step(steps)
+    m, U, Ut = g.moments()
+    mo, Uo, Uto = red.moments()
+    sdt = np.sin(case.meta["dtheta"])
+    r_c = case.meta["centres"]
+    uth = Ut.reshape(256, 1024, 2)[:, 0, 1] * r_c * sdt
+    uth_o = Uto[:, 1] * r_c * sdt
+    err = np.abs(uth - uth_o).max()
+    say("u_theta err vs reduced oracle", err, "U", 0.05)
+    assert err <= tolu * 0.05
+    e1 = _one_step_sampled(g, case)
+    say("one-step sampled rel err", e1)
+    assert e1 <= tol1
+
+
+@pytest.mark.parametrize("Ny,tau", [(64, 0.6), (64, 1.0), (128, 0.6), (128, 1.0), (256, 0.6), (256, 1.0),
+                                    (512, 0.6), (512, 1.0)])
+def test_planar_poiseuille_stretched(Ny, tau):
+    """The 16 x Ny channels stretched by 1.02 per cell from both walls.  Stable
+    cases: FP64 velocity equals the exact x-reduction on the oracle and the
+    one-step parity holds in FP64 and FP32; cases whose wall cells leave the
+    equilibrium's stability range blow up on both, and the library reports
+    LBM_EUNSTABLE."""
+    case = G.workload_planar_poiseuille(Ny, tau)
+    steps = 1000
+    g = lbm.Grid(case, precision=lbm.LBM_FP64)
+    g.init()
+    g.step(steps)
+    red = oracle.OracleGrid(G.workload_planar_poiseuille(Ny, tau, n_per=1))
+    red.init(1.0)
+    red.step(steps)
+    mo, Uo, Uto = red.moments()
+    r = g.residual(check=False)
+    stable_o = bool(np.isfinite(Uto).all() and np.isfinite(mo).all())
+    say("poiseuille", Ny, tau, "gpu bad cells", r.bad_cells, "oracle finite", stable_o)
+    if not stable_o:
+        assert r.bad_cells > 0
+        with pytest.raises(lbm.LbmError) as e:
+            g.residual()
+        assert e.value.code == lbm.LBM_EUNSTABLE
+        return
+    assert r.bad_cells == 0
+    m, U, Ut = g.moments()
+    Ut0 = Ut.reshape(case.n1, case.n2, 2)[:, 0]
+    assert np.abs(Ut0 - Uto).max() <= 1e-12 * max(np.abs(Uto).max(), 1e-9)
+    for prec, tol1 in ((lbm.LBM_FP64, 1e-13), (lbm.LBM_FP32, 3e-6)):
+        g = lbm.Grid(case, precision=prec)
+        g.init()
+        g.step(300)
+        e1 = _one_step_sampled(g, case, nsample=min(1500, case.ncell // 2))
+        say("poiseuille", Ny, tau, prec, "one-step", e1)
+        assert e1 <= tol1
