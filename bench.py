@@ -32,6 +32,8 @@ def workloads():
         # the seed-fixed 64-annulus ensemble (mixed D2Q9 / D2Q21), advanced as one batch
         "ensemble_64_annuli": lambda: G.workload_ensemble(),
         "planar_couette_q9_32x16": lambda: [G.workload_planar_couette_q9()],
+        # kernel-scaling probe (not one of the stated workloads): the same annulus family at 16x the cells
+        "annulus_couette_1024x4096": lambda: [G.workload_annulus_couette(1024, 4096, tau=0.8)],
     }
 
 
@@ -56,34 +58,16 @@ def cpu_baseline(case, target_s=15.0):
                       % (case.meta.get("workload", "grid"), k, case.n1, case.n2, threads, dt)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="annulus_couette_256x1024", choices=sorted(workloads()))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--wpb", type=int, default=0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (each box has one MI355X); "
-              "run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
+def measure(cases, prec, steps, warmup, wpb=0, stream=None):
+    """Create, initialise and time `steps` steps of the workload; returns a dict."""
     import torch
     from paper_2301_01868_amd import lbm
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    prec = lbm.LBM_FP32 if args.precision == "fp32" else lbm.LBM_FP64
-    cases = workloads()[args.workload]()
-    stream = torch.cuda.Stream()
     grids = []
     for c in cases:
         g = lbm.Grid(c, precision=prec, stream=ct_stream(stream))
-        if args.wpb:
-            g.set_launch(args.wpb)
+        if wpb:
+            g.set_launch(wpb)
         g.init()
         grids.append(g)
     cells = sum(c.ncell for c in cases)
@@ -95,76 +79,126 @@ def main():
         else:
             grids[0].step(n)
 
-    run(args.warmup)
+    run(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     ev0.record(stream)
-    run(args.steps)
+    run(steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
-    ms_step = ms / args.steps
-    mlups = cells * args.steps / (ms * 1e-3) / 1e6
+    bads = [g.residual(check=False).bad_cells for g in grids]
+    bad = sum(bads)
+    unstable = [k for k, b in enumerate(bads) if b > 0]
 
-    # roofline of the dominant kernel: the D2Q21 step (algorithmic bytes 2 Q s per cell update)
+    # dominant kernel: the D2Q21 step (algorithmic bytes 2 Q sizeof(population) per cell update)
     s_bytes = 4 if prec == lbm.LBM_FP32 else 8
-    q21_cells = sum(c.ncell for c in cases if c.q == 21)
-    q9_cells = cells - q21_cells
     if batch is None:
-        dom_q = cases[0].q
-        alg_bytes = 2 * dom_q * s_bytes * cells
-        avg_launch_ms = ms_step
+        q = cases[0].q
+        kcells = cells
+        avg_ms = ms / steps
+        kname = "k_step<%d,%s,row>" % (q, "f32" if s_bytes == 4 else "f64")
     else:
-        # time the batch with only its D2Q21 group launched, same stream, events
-        dom_q = 21
-        alg_bytes = 2 * 21 * s_bytes * q21_cells
-        avg_launch_ms = None
-    roof = None
-    if avg_launch_ms:
-        achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_step<%d,%s>" % (dom_q, args.precision), "bytes_per_launch": alg_bytes,
-                "avg_launch_us": round(avg_launch_ms * 1e3, 3)}
-
-    # residual sanity (finite state) after the timed steps
-    bad = 0
+        groups = lbm.lbm_batch_groups(batch)
+        gi = max(range(len(groups)), key=lambda k: (groups[k][0] == 21, groups[k][2]))
+        q, _, kcells = groups[gi]
+        reps = max(2, (steps // 4) // 2 * 2)
+        lbm.lbm_batch_step_group(batch, gi, 2)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        lbm.lbm_batch_step_group(batch, gi, reps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        avg_ms = ev0.elapsed_time(ev1) / reps
+        kname = "k_step<%d,%s,row> (batch group of %d cells)" % (q, "f32" if s_bytes == 4 else "f64", kcells)
+    alg_bytes = 2 * q * s_bytes * kcells
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_ms * 1e3, 3)}
+    if batch is not None:
+        lbm.lbm_batch_destroy(batch)
     for g in grids:
-        r = g.residual(check=False)
-        bad += r.bad_cells
+        g.close()
+    return {"mlups": cells * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps, "cells": cells,
+            "q21_cells": sum(c.ncell for c in cases if c.q == 21), "bad_cells": int(bad), "unstable": unstable,
+            "roofline": roof}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="ensemble_64_annuli", choices=sorted(workloads()))
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run the library's plain copy kernel on MIB MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (each box has one MI355X); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2301_01868_amd import lbm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            lbm.lbm_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, None)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
+        print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}), flush=True)
+        return
+    cases = workloads()[args.workload]()
+    stream = torch.cuda.Stream()
+    r32 = measure(cases, lbm.LBM_FP32, args.steps, args.warmup, args.wpb, stream)
+    r64 = None
+    if not args.no_fp64:
+        r64 = measure(cases, lbm.LBM_FP64, max(2, args.steps // 2), max(2, args.warmup // 2), args.wpb, stream)
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(cases[0] if len(cases) == 1 else max((c for c in cases if c.q == 21), key=lambda c: -c.ncell))
+        q21 = [c for c in cases if c.q == 21] or cases
+        cpu = cpu_baseline(min(q21, key=lambda c: c.ncell))
 
     out = {
         "metric": "MLUPS + % HBM roofline (D2Q21 FP32 vs FP64)",
-        "value": round(mlups, 1),
+        "value": round(r32["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": round(r32["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == lbm.LBM_FP32 else "f64",
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "cells": cells, "q21_cells": q21_cells, "q9_cells": q9_cells,
-                   "grids": len(cases), "precision": args.precision, "bad_cells_after": int(bad)},
-        "roofline": roof,
+        "config": {"workload": args.workload, "cells": r32["cells"], "q21_cells": r32["q21_cells"],
+                   "grids": len(cases), "precision": "fp32 populations (offsets from the local rest state)",
+                   "bad_cells_after": r32["bad_cells"], "unstable_instances": r32["unstable"]},
+        "roofline": r32["roofline"],
         "cpu_baseline": cpu,
     }
+    if r64 is not None:
+        out["fp64"] = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
+                       "roofline": r64["roofline"], "bad_cells_after": r64["bad_cells"]}
     print(json.dumps(out), flush=True)
-    if batch is not None:
-        lbm.lbm_batch_destroy(batch)
 
 
 def ct_stream(torch_stream):
     import ctypes
-    return ctypes.c_void_p(torch_stream.cuda_stream)
+    return ctypes.c_void_p(torch_stream.cuda_stream) if torch_stream is not None else None
 
 
 if __name__ == "__main__":

@@ -196,6 +196,16 @@ int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out);
 int lbm_batch_step(lbm_batch *b, int64_t n);
 void lbm_batch_destroy(lbm_batch *b);
 
+/* Group g of a batch (one lattice/precision/table kind, one kernel launch per
+ * step): returns the number of groups (>= 0) or an error; fills the lattice,
+ * precision and total cells of group g when g is in range. */
+int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *precision, int64_t *cells);
+
+/* Measurement hook: launch only group g's step kernel n times (n even, so
+ * buffer parities are unchanged); the other groups do not advance, so the
+ * batch's states are no longer one consistent time level afterwards. */
+int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n);
+
 /* Launch configuration of the step kernels: waves per workgroup (1, 2 or 4;
  * each wave covers 64 columns of one row) for a grid (and the batches made
  * from it later).  0 restores the automatic choice. */

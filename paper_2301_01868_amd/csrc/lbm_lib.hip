@@ -914,6 +914,35 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
     return LBM_OK;
 }
 
+int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *precision, int64_t *cells)
+{
+    if (!b) return fail(nullptr, LBM_EINVAL, "null batch");
+    if (group < 0 || group >= (int32_t)b->groups.size()) return fail(nullptr, LBM_EINVAL, "no such group");
+    const auto &G = b->groups[group];
+    if (q) *q = G.q;
+    if (precision) *precision = G.precision;
+    if (cells) {
+        int64_t c = 0;
+        for (lbm_grid *g : b->grids)
+            if (g->q == G.q && g->precision == G.precision && (g->row ? 0 : 1) == G.cell) c += g->ncell;
+        *cells = c;
+    }
+    return (int)b->groups.size();
+}
+
+int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n)
+{
+    if (!b || group < 0 || group >= (int32_t)b->groups.size() || n < 0 || (n & 1))
+        return fail(nullptr, LBM_EINVAL, "bad group step arguments (n must be even)");
+    const auto &G = b->groups[group];
+    StepFn fn = pick_step(G.q, G.precision, G.cell, 0);
+    for (int64_t k = 0; k < n; ++k)
+        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), 0, b->stream, (const InstDesc *)G.d_inst,
+                           (const int4 *)G.d_tiles, (int)((b->step + k) & 1));
+    if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "group step launch failed");
+    return LBM_OK;
+}
+
 int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream)
 {
     if (!dst || !src || (bytes & 15)) return fail(nullptr, LBM_EINVAL, "copy probe needs 16-byte multiples");

@@ -24,7 +24,7 @@ BC = {"periodic": LBM_PERIODIC, "noslip": LBM_NOSLIP, "moving": LBM_MOVING}
 EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_error", "lbm_grid_info_get",
             "lbm_set_volume", "lbm_get_volume", "lbm_init", "lbm_step", "lbm_moments", "lbm_residual", "lbm_noflow_adjust",
             "lbm_get_state", "lbm_set_state", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
-            "lbm_stream", "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_set_launch",
+            "lbm_stream", "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch",
             "lbm_copy_probe"]
 
 
@@ -101,6 +101,8 @@ def load():
     L.lbm_batch_step.argtypes = [vp, ct.c_int64]
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_destroy.restype = None
+    L.lbm_batch_info.argtypes = [vp, ct.c_int32, I32, I32, ct.POINTER(ct.c_int64)]
+    L.lbm_batch_step_group.argtypes = [vp, ct.c_int32, ct.c_int64]
     L.lbm_set_launch.argtypes = [vp, ct.c_int32]
     L.lbm_copy_probe.argtypes = [vp, vp, ct.c_size_t, vp]
     _lib = L
@@ -257,6 +259,27 @@ def lbm_batch_step(b, n):
 
 def lbm_batch_destroy(b):
     load().lbm_batch_destroy(b)
+
+
+def lbm_batch_info(b, group):
+    q = ct.c_int32()
+    prec = ct.c_int32()
+    cells = ct.c_int64()
+    n = load().lbm_batch_info(b, int(group), ct.byref(q), ct.byref(prec), ct.byref(cells))
+    if n < 0:
+        _chk(n)
+    return n, q.value, prec.value, cells.value
+
+
+def lbm_batch_groups(b):
+    n = load().lbm_batch_info(b, 0, None, None, None)
+    if n < 0:
+        _chk(n)
+    return [lbm_batch_info(b, k)[1:] for k in range(n)]
+
+
+def lbm_batch_step_group(b, group, n):
+    _chk(load().lbm_batch_step_group(b, int(group), int(n)))
 
 
 def lbm_copy_probe(dst_ptr, src_ptr, nbytes, stream=None):
