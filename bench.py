@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -68,6 +70,8 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None):
         g = lbm.Grid(c, precision=prec, stream=ct_stream(stream))
         if wpb:
             g.set_launch(wpb)
+        else:
+            g.autotune(10)
         g.init()
         grids.append(g)
     cells = sum(c.ncell for c in cases)
@@ -93,12 +97,13 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None):
     unstable = [k for k, b in enumerate(bads) if b > 0]
 
     # dominant kernel: the D2Q21 step (algorithmic bytes 2 Q sizeof(population) per cell update)
-    s_bytes = 4 if prec == lbm.LBM_FP32 else 8
+    s_bytes = {lbm.LBM_FP64: 8, lbm.LBM_FP32: 4, lbm.LBM_FP16: 2}[prec]
+    sname = {8: "f64", 4: "f32", 2: "f16"}[s_bytes]
     if batch is None:
         q = cases[0].q
         kcells = cells
         avg_ms = ms / steps
-        kname = "k_step<%d,%s,row>" % (q, "f32" if s_bytes == 4 else "f64")
+        kname = "k_step<%d,%s,row>" % (q, sname)
     else:
         groups = lbm.lbm_batch_groups(batch)
         gi = max(range(len(groups)), key=lambda k: (groups[k][0] == 21, groups[k][2]))
@@ -111,7 +116,7 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None):
         ev1.record(stream)
         torch.cuda.synchronize()
         avg_ms = ev0.elapsed_time(ev1) / reps
-        kname = "k_step<%d,%s,row> (batch group of %d cells)" % (q, "f32" if s_bytes == 4 else "f64", kcells)
+        kname = "k_step<%d,%s,row> (batch group of %d cells)" % (q, sname, kcells)
     alg_bytes = 2 * q * s_bytes * kcells
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -135,6 +140,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--wpb", type=int, default=0)
+    ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark: continuous batching vs sequential FP64 on a Poisson trace")
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--duration", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the library's plain copy kernel on MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -152,12 +162,33 @@ def main():
         nbytes = args.copy_probe << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        stream = torch.cuda.Stream()
         torch.cuda.synchronize()
         for _ in range(5):
-            lbm.lbm_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, None)
+            lbm.lbm_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, ct_stream(stream))
         torch.cuda.synchronize()
         assert torch.equal(src, dst)
-        print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}), flush=True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        reps = 20
+        ev0.record(stream)
+        for _ in range(reps):
+            lbm.lbm_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, ct_stream(stream))
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            for _ in range(reps):
+                dst.copy_(src)
+            ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_t = ev0.elapsed_time(ev1) / reps
+        print(json.dumps({"copy_probe_bytes": nbytes, "k_copy_GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1),
+                          "torch_copy_GBps": round(2 * nbytes / (ms_t * 1e-3) / 1e9, 1)}), flush=True)
+        return
+    if args.serve:
+        serve_bench(args)
         return
     cases = workloads()[args.workload]()
     stream = torch.cuda.Stream()
@@ -165,6 +196,9 @@ def main():
     r64 = None
     if not args.no_fp64:
         r64 = measure(cases, lbm.LBM_FP64, max(2, args.steps // 2), max(2, args.warmup // 2), args.wpb, stream)
+    r16 = None
+    if not args.no_fp16:
+        r16 = measure(cases, lbm.LBM_FP16, args.steps, args.warmup, args.wpb, stream)
 
     cpu = None
     if not args.no_cpu:
@@ -193,6 +227,47 @@ def main():
     if r64 is not None:
         out["fp64"] = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
                        "roofline": r64["roofline"], "bad_cells_after": r64["bad_cells"]}
+    if r16 is not None:
+        out["fp16"] = {"value": round(r16["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r16["ms_per_step"], 5),
+                       "roofline": r16["roofline"], "bad_cells_after": r16["bad_cells"]}
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Serving: Poisson arrivals of steady-state solves, continuous batching in
+    FP32 against plain sequential FP64 stepping, both to the same residual."""
+    import copy
+    import torch
+    from paper_2301_01868_amd import serve, lbm
+
+    stream = torch.cuda.Stream()
+    trace = serve.make_trace(rate=args.rate, duration=args.duration)
+    base = copy.deepcopy(trace)
+    srv = serve.Server(hbm_budget=8 << 30, check_every=200, stream=ct_stream(stream))
+    info = srv.run(trace, realtime=True)
+    s_b = serve.summarize(trace, info["makespan"])
+    info2 = serve.run_sequential(base, stream=ct_stream(stream), realtime=True)
+    s_s = serve.summarize(base, info2["makespan"])
+    # equal accuracy: both converged to the same residual; compare the velocity fields
+    diffs = []
+    worst = []
+    for a, b in zip(trace, base):
+        if a.status == "converged" and b.status == "converged":
+            # physical velocity u = Ut^i g_i compared against the case's speed scale
+            U = max(np.abs(b.result["Ut"]).max(), 1e-3)
+            dv = float(np.abs(a.result["Ut"] - b.result["Ut"]).max() / U)
+            diffs.append(dv)
+            worst.append((dv, a.case.meta.get("problem"), a.case.q, a.case.n1, round(a.case.tau, 3), a.steps, b.steps))
+    worst.sort(reverse=True)
+    out = {"metric": "solves/s, p50/p99 latency (serving)", "value": round(s_b["solves_per_s"], 3),
+           "unit": "solves/s", "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": "poisson_trace", "rate_per_s": args.rate, "duration_s": args.duration,
+                      "requests": len(trace), "tol": 1e-8},
+           "batched_fp32": s_b, "sequential_fp64": s_s,
+           "speedup_solves_per_s": round(s_b["solves_per_s"] / max(s_s["solves_per_s"], 1e-12), 2),
+           "max_rel_velocity_diff_fp32_vs_fp64": max(diffs) if diffs else None,
+           "median_rel_velocity_diff_fp32_vs_fp64": float(np.median(diffs)) if diffs else None,
+           "worst_requests": worst[:4]}
     print(json.dumps(out), flush=True)
 
 

@@ -52,7 +52,9 @@ enum { LBM_PERIODIC = 0, LBM_NOSLIP = 1, LBM_MOVING = 2 };
 /* population storage / arithmetic */
 enum {
     LBM_FP64 = 0,   /* FP64 populations, FP64 arithmetic */
-    LBM_FP32 = 1    /* FP32 populations stored as offsets from a per-cell base, FP32 arithmetic */
+    LBM_FP32 = 1,   /* FP32 populations stored as offsets from a per-cell base, FP32 arithmetic */
+    LBM_FP16 = 2    /* FP16 offsets divided by the direction's lattice weight (per-plane scaling),
+                       FP32 arithmetic; the error against FP64 is the caller's to measure */
 };
 
 /* offset base for LBM_FP32 storage: the stored value is N_alpha - B_alpha */
@@ -90,7 +92,7 @@ typedef struct {
     double tau;             /* BGK relaxation time, > 1/2 */
     double accel[2];        /* constant external acceleration, contravariant components */
     double rho0;            /* reference density (initial state and offset base) */
-    int32_t precision;      /* LBM_FP64 | LBM_FP32 */
+    int32_t precision;      /* LBM_FP64 | LBM_FP32 | LBM_FP16 */
     int32_t offset_base;    /* LBM_BASE_* (ignored for LBM_FP64) */
     int32_t iterations;     /* 0: force with the lagged N'(q, t-1) (Sec. 2); k > 0: k extra
                                fixed-point passes of the implicit force relation */
@@ -191,10 +193,17 @@ void *lbm_stream(lbm_grid *g);
 
 /* Many grids advanced together: one launch per lattice and precision per step
  * over a flattened table of row tiles; steps of a batch are captured in HIP
- * graphs.  All grids must share the stream of grids[0]. */
+ * graphs and run on the stream of grids[0] (grids on other streams are joined
+ * with events before and after).  Every grid must be initialised; while it is
+ * in a batch a grid must only be stepped through the batch. */
 int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out);
 int lbm_batch_step(lbm_batch *b, int64_t n);
 void lbm_batch_destroy(lbm_batch *b);
+
+/* Residuals of every grid of the batch (out[n], batch order) with one
+ * synchronisation; same definitions as lbm_residual.  Returns LBM_EUNSTABLE
+ * (after filling every record) if any grid has bad cells. */
+int lbm_batch_residuals(lbm_batch *b, lbm_resid *out);
 
 /* Group g of a batch (one lattice/precision/table kind, one kernel launch per
  * step): returns the number of groups (>= 0) or an error; fills the lattice,
@@ -206,10 +215,18 @@ int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *preci
  * batch's states are no longer one consistent time level afterwards. */
 int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n);
 
-/* Launch configuration of the step kernels: waves per workgroup (1, 2 or 4;
- * each wave covers 64 columns of one row) for a grid (and the batches made
- * from it later).  0 restores the automatic choice. */
+/* Launch configuration of the step kernels for a grid (and the batches made
+ * from it later): waves per workgroup (1, 2 or 4; each wave covers 64
+ * columns of one row; 0 = default 4). */
 int lbm_set_launch(lbm_grid *g, int32_t waves_per_block);
+
+/* Autotuner: times `steps` step launches for each tile shape (1, 2 or 4
+ * waves, i.e. rows, per workgroup), keeps the fastest and caches the choice
+ * for the process per (q, precision, table kind, n1, n2).  The timing steps
+ * run on the grid's own buffers, so call it between create and init (the
+ * grid needs lbm_init afterwards).  Returns the chosen waves per workgroup
+ * (> 0) or an error code. */
+int lbm_autotune(lbm_grid *g, int32_t steps);
 
 /* Plain device copy kernel (for calibrating memory-traffic counters). */
 int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream);

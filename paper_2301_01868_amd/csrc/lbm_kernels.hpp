@@ -46,13 +46,22 @@ template <int Q>
 struct Tab {
     static constexpr int G11 = 0, G12 = 1, G22 = 2, MB = 3, C1 = 4, C2 = 5, D0 = 6, PHIB0 = 7;
     static constexpr int NP = npair<Q>();
+    // per direction a = 1..Q-1: A+^1_a, A+^2_a, base difference of the pulled source
     __host__ __device__ static constexpr int A1(int a) { return 8 + 3 * (a - 1); }
     __host__ __device__ static constexpr int A2(int a) { return 8 + 3 * (a - 1) + 1; }
     __host__ __device__ static constexpr int DB(int a) { return 8 + 3 * (a - 1) + 2; }
-    __host__ __device__ static constexpr int K(int p) { return 8 + 3 * (Q - 1) + 3 * p; }
-    __host__ __device__ static constexpr int D(int p) { return 8 + 3 * (Q - 1) + 3 * p + 1; }
-    __host__ __device__ static constexpr int PHIB(int p) { return 8 + 3 * (Q - 1) + 3 * p + 2; }
-    static constexpr int W = 8 + 3 * (Q - 1) + 3 * NP;
+    // per +-c pair p: K (odd equilibrium coefficient), D (even rest part minus
+    // the base's share), PHIB (the base's share), and the momentum-flux weights
+    // X11 = k c1 S1, X12 = k (c1 S2 + c2 S1), X22 = k c2 S2 with
+    // S^j = A+^j_a + A+^j_{-a} and k = -(1 - 1/(2 tau))
+    __host__ __device__ static constexpr int PB(int p) { return 8 + 3 * (Q - 1) + 6 * p; }
+    __host__ __device__ static constexpr int K(int p) { return PB(p); }
+    __host__ __device__ static constexpr int D(int p) { return PB(p) + 1; }
+    __host__ __device__ static constexpr int PHIB(int p) { return PB(p) + 2; }
+    __host__ __device__ static constexpr int X11(int p) { return PB(p) + 3; }
+    __host__ __device__ static constexpr int X12(int p) { return PB(p) + 4; }
+    __host__ __device__ static constexpr int X22(int p) { return PB(p) + 5; }
+    static constexpr int W = 8 + 3 * (Q - 1) + 6 * NP;
     static constexpr int STRIDE = (W + 3) & ~3;   // row stride, 16-byte multiple for FP32
 };
 
@@ -60,6 +69,7 @@ struct Tab {
 struct InstDesc {
     void *P[2];          // population storage buffers, [Q][n1][pitch]
     void *side[2];       // moving-wall side state, [2 walls][2 fields][hw][pitch]
+    void *lag[2];        // lagged own-cell force sums sum_a A+^i_a s_a, [2][n1][pitch] (compute type)
     const void *tab;     // step table
     double *mom;         // moments output [5][ncell] (m, U1, U2, Ut1, Ut2)
     const double *mB64;  // FP64 base mass per table entry
@@ -136,6 +146,49 @@ __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t 
     }
 }
 
+// Population storage encoding.  FP64 and FP32 store the (offset) value as is;
+// FP16 stores it divided by the direction's lattice weight, which brings the
+// offsets of every direction to the same magnitude (per-plane scaling; the
+// bounce-back and specular partners share the weight).
+template <int Q, typename S>
+__host__ __device__ constexpr double plane_scale(int a)
+{
+    if constexpr (sizeof(S) == 2) return weight<Q>(a);
+    else return 1.0;
+}
+template <int Q, typename S, typename T>
+__device__ inline T pload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, int a)
+{
+    if constexpr (sizeof(S) == 2) {
+        const _Float16 h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+        return (T)h * (T)plane_scale<Q, S>(a);
+    } else {
+        return bload<S, T>(r, voff, soff);
+    }
+}
+template <int Q, typename S, typename T>
+__device__ inline S penc(T v, int a)
+{
+    if constexpr (sizeof(S) == 2) return (S)(v * (T)(1.0 / plane_scale<Q, S>(a)));
+    else return (S)v;
+}
+template <int Q, typename S, typename T>
+__device__ inline T pdec(S v, int a)
+{
+    if constexpr (sizeof(S) == 2) return (T)v * (T)plane_scale<Q, S>(a);
+    else return (T)v;
+}
+template <int Q, typename S, typename T>
+__device__ inline void pstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, int a, T v)
+{
+    if constexpr (sizeof(S) == 2) {
+        using U16 = decltype(__builtin_amdgcn_raw_buffer_load_b16(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(U16, penc<Q, S, T>(v, a)), r, voff, soff, 0);
+    } else {
+        bstore<S, T>(r, voff, soff, v);
+    }
+}
+
 // uniform (scalar-cache) view of a row table
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T *;
@@ -167,7 +220,6 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
     constexpr int CM = cmax<Q>();
     constexpr int NP = npair<Q>();
     constexpr double T0d = lattice_T0<Q>();
-    constexpr T T0 = (T)T0d;
     using TB = Tab<Q>;
 
     const int4 tl = tiles[blockIdx.x];
@@ -176,13 +228,13 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
     const int i = tl.y + wave;
     const int n1 = d->n1, n2 = d->n2;
     if (i >= n1) return;
-    const int j = tl.z + (int)(threadIdx.x & 63);
+    const int j0 = tl.z;
+    const int j = j0 + (int)(threadIdx.x & 63);
     if (j >= n2) return;
 
     const int pitch = d->pitch, hw = d->hw;
     const long long plane = d->plane;
     const int pin = (par ^ d->par0) & 1;
-    const S *__restrict__ Pin = (const S *)d->P[pin];
     const int bclo = d->bc_lo, bchi = d->bc_hi, per1 = d->periodic1;
 
     TabView<T, CELL> tb;
@@ -194,32 +246,34 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
         tb.s = 1;
     }
 
-    // byte offsets of the wrapped columns j - c2, c2 = -CM..CM (q2 is periodic)
     constexpr uint32_t ES = sizeof(S);
-    uint32_t colb[2 * CM + 1];
-    if (n2 >= CM) {
-#pragma unroll
-        for (int k = -CM; k <= CM; ++k) colb[k + CM] = (uint32_t)wrap_col(j - k, n2) * ES;
-    } else {
-#pragma unroll
-        for (int k = -CM; k <= CM; ++k) colb[k + CM] = (uint32_t)(((j - k) % n2 + n2) % n2) * ES;
-    }
-    const uint32_t pbytes = (uint32_t)(plane * Q) * ES;
-    const __amdgpu_buffer_rsrc_t rin = make_rsrc(Pin, pbytes);
     const uint32_t plane_b = (uint32_t)plane * ES, pitch_b = (uint32_t)pitch * ES;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(d->P[pin], (uint32_t)(plane * Q) * ES);
+    const uint32_t jb = (uint32_t)j * ES;
 
     // ---- pull streaming with boundary sources ----
     T n[Q], s[Q];
     const bool interior = (i >= CM && i < n1 - CM);
-    if (interior) {
-        // rows whose whole stencil stays inside: source row i - c1, same direction
+    const bool nowrap = (j0 >= CM) && (j0 + 63 + CM < n2);
+    if (interior && nowrap) {
+        // the whole stencil of the wave stays inside: source (i - c1, j - c2),
+        // same direction; the column shift rides in the scalar offset
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
-            const uint32_t soff = (uint32_t)a * plane_b + (uint32_t)(i - cx(a)) * pitch_b;
-            n[a] = bload<S, T>(rin, colb[cy(a) + CM], soff);
+            const uint32_t soff = (uint32_t)((int)(a * plane_b + (i - cx(a)) * pitch_b) - cy(a) * (int)ES);
+            n[a] = pload<Q, S, T>(rin, jb, soff, a);
             if (a > 0) n[a] += tb(TB::DB(a));
         }
     } else {
+        // byte offsets of the wrapped columns j - c2, c2 = -CM..CM (q2 is periodic)
+        uint32_t colb[2 * CM + 1];
+        if (n2 >= CM) {
+#pragma unroll
+            for (int k = -CM; k <= CM; ++k) colb[k + CM] = (uint32_t)wrap_col(j - k, n2) * ES;
+        } else {
+#pragma unroll
+            for (int k = -CM; k <= CM; ++k) colb[k + CM] = (uint32_t)(((j - k) % n2 + n2) % n2) * ES;
+        }
         const T *side_in = (const T *)d->side[pin];
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
@@ -227,7 +281,7 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
             int r, beta, wall;
             pull_source(i, a, n1, per1, bclo, bchi, r, beta, wall);
             const uint32_t cb = colb[c2 + CM];
-            T v = bload<S, T>(rin, cb, (uint32_t)beta * plane_b + (uint32_t)r * pitch_b);
+            T v = pload<Q, S, T>(rin, cb, (uint32_t)beta * plane_b + (uint32_t)r * pitch_b, a);
             if (a > 0) v += tb(TB::DB(a));
             if (c2 != 0 && wall != 0) {
                 const int sd = wall - 1;
@@ -244,42 +298,56 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
             n[a] = v;
         }
     }
-    // own post-collision values N'(q, t-1) for the lagged force
-    const uint32_t jb = (uint32_t)j * ES;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) s[a] = bload<S, T>(rin, jb, (uint32_t)a * plane_b + (uint32_t)i * pitch_b);
+    // lagged own-cell force sums sum_a A+^i_a s_a(q, t-1), formed when the
+    // previous step produced N'(q, t-1)
+    constexpr uint32_t ET = sizeof(T);
+    const uint32_t lplane_b = (uint32_t)plane * ET;
+    const __amdgpu_buffer_rsrc_t rlag = make_rsrc(d->lag[pin], 2 * lplane_b);
+    const uint32_t jt = (uint32_t)j * ET, rowt = (uint32_t)i * pitch * ET;
+    const T Lo1 = bload<T, T>(rlag, jt, rowt);
+    const T Lo2 = bload<T, T>(rlag, jt, lplane_b + rowt);
 
-    // ---- moments ----
-    T dm = 0, mU1 = 0, mU2 = 0;
+    // ---- moments (in +-c pairs) ----
+    T dm = n[0], mU1 = 0, mU2 = 0;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-        dm += n[a];
-        if (cx(a) != 0) mU1 += (T)cx(a) * n[a];
-        if (cy(a) != 0) mU2 += (T)cy(a) * n[a];
+    for (int p = 0; p < NP; ++p) {
+        const int a = pair_rep(p), b = opp(a);
+        const T sp = n[a] + n[b], dp = n[a] - n[b];
+        dm += sp;
+        if (cx(a) != 0) mU1 += (T)cx(a) * dp;
+        if (cy(a) != 0) mU2 += (T)cy(a) * dp;
     }
     const T m = tb(TB::MB) + dm;
-    const T im = (T)1 / m;
+    T im;
+    if constexpr (sizeof(T) == 4) im = __builtin_amdgcn_rcpf(m);   // 1-ulp hardware reciprocal
+    else im = 1.0 / m;
     const T U1 = mU1 * im, U2 = mU2 * im;
-
-    // ---- force: the part independent of the lagged own-cell values ----
-    T Ln1 = tb(TB::C1), Ln2 = tb(TB::C2);
-#pragma unroll
-    for (int a = 1; a < Q; ++a) {
-        Ln1 += tb(TB::A1(opp(a))) * n[a];
-        Ln2 += tb(TB::A2(opp(a))) * n[a];
-    }
     const T ma1 = m * (T)d->a1, ma2 = m * (T)d->a2;
     const T G11 = tb(TB::G11), G12 = tb(TB::G12), G22 = tb(TB::G22);
-    const T omega = (T)d->omega, kpi = (T)d->kpi;
+    const T omega = (T)d->omega, omw = (T)1 - (T)d->omega;
     const int iters = MOM ? 0 : d->iters;
 
     T JF1, JF2, Ut1, Ut2;
-    for (int it = 0;; ++it) {
-        T L1 = Ln1, L2 = Ln2;
+    // pulled part of the force sum: sum_a A+_a n_{-a} (pass independent)
+    T Ln1 = tb(TB::C1), Ln2 = tb(TB::C2);
 #pragma unroll
-        for (int a = 1; a < Q; ++a) {
-            L1 += tb(TB::A1(a)) * s[a];
-            L2 += tb(TB::A2(a)) * s[a];
+    for (int p = 0; p < NP; ++p) {
+        const int a = pair_rep(p), b = opp(a);
+        Ln1 += tb(TB::A1(a)) * n[b] + tb(TB::A1(b)) * n[a];
+        Ln2 += tb(TB::A2(a)) * n[b] + tb(TB::A2(b)) * n[a];
+    }
+    for (int it = 0;; ++it) {
+        // ---- force: J F = -1/2 [C + sum_a A+_a (s_a + n_{-a})] + m a_ext ----
+        T L1 = Ln1, L2 = Ln2;
+        if (it == 0) {
+            L1 += Lo1;
+            L2 += Lo2;
+        } else {
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                L1 += tb(TB::A1(a)) * s[a];
+                L2 += tb(TB::A2(a)) * s[a];
+            }
         }
         JF1 = (T)-0.5 * L1 + ma1;
         JF2 = (T)-0.5 * L2 + ma2;
@@ -287,66 +355,56 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
         Ut2 = U2 + (T)0.5 * JF2 * im;
         if constexpr (MOM) break;
 
-        // ---- equilibrium (pair form) and momentum-flux correction ----
+        // ---- odd part of the equilibrium and the momentum-flux correction ----
         const T GU1 = G11 * Ut1 + G12 * Ut2;
         const T GU2 = G12 * Ut1 + G22 * Ut2;
         const T uu = Ut1 * Ut1 + Ut2 * Ut2;
-        T Ev[NP], Od[NP];
-        T P11 = 0, P12 = 0, P21 = 0, P22 = 0;
+        const T uu3 = (T)(3.0 * T0d) * uu;
+        const T uuT = (T)T0d * uu;
+        T mO[NP], cUt[NP];
+        T P11 = 0, P12 = 0, P22 = 0;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const int a = pair_rep(p), b = opp(a);
+            const int a = pair_rep(p);
             const int c1 = cx(a), c2 = cy(a);
             const double w = weight<Q>(a);
             const double cc = (double)(c1 * c1 + c2 * c2);
             const T cU = (T)c1 * U1 + (T)c2 * U2;
-            const T cUt = (T)c1 * Ut1 + (T)c2 * Ut2;
+            const T cut = (T)c1 * Ut1 + (T)c2 * Ut2;
             const T cGU = (T)c1 * GU1 + (T)c2 * GU2;
+            const T q3 = (cut * cut - uu3) * cut;
             const T O = (T)(w * (1.0 / T0d + (4.0 * T0d - cc) / (2.0 * T0d * T0d))) * cU - (T)(w / T0d) * cGU +
-                        (T)(w / (6.0 * T0d * T0d * T0d)) * (cUt * cUt - (T)3 * T0 * uu) * cUt +
-                        tb(TB::K(p)) * cUt;
-            const T E = tb(TB::D(p)) + (T)(w / (2.0 * T0d)) * (cUt * cUt * (T)(1.0 / T0d) - uu);
-            Ev[p] = E;
-            Od[p] = O;
-            const T mO = m * O;
-            const T S1 = tb(TB::A1(a)) + tb(TB::A1(b));
-            const T S2 = tb(TB::A2(a)) + tb(TB::A2(b));
-            if (c1 != 0) {
-                P11 += (T)c1 * S1 * mO;
-                P12 += (T)c1 * S2 * mO;
-            }
-            if (c2 != 0) {
-                P21 += (T)c2 * S1 * mO;
-                P22 += (T)c2 * S2 * mO;
-            }
+                        (T)(w / (6.0 * T0d * T0d * T0d)) * q3 + tb(TB::K(p)) * cut;
+            const T mo = m * O;
+            mO[p] = mo;
+            cUt[p] = cut;
+            if (c1 != 0) P11 += tb(TB::X11(p)) * mo;
+            if (c2 != 0) P22 += tb(TB::X22(p)) * mo;
+            P12 += tb(TB::X12(p)) * mo;
         }
-        P11 *= kpi;
-        P12 *= kpi;
-        P21 *= kpi;
-        P22 *= kpi;
         const T trP = P11 + P22;
-        const T P12s = P12 + P21;
 
-        // ---- curvilinear correction + BGK (offset form) ----
+        // ---- even part, curvilinear correction and BGK (offset form) ----
         {
             constexpr double w0 = weight<Q>(0);
             const T feq0 = m * (tb(TB::D0) - (T)(w0 / (2.0 * T0d)) * uu) + dm * tb(TB::PHIB0);
-            s[0] = n[0] - omega * (n[0] - feq0) - (T)(w0 / T0d) * trP;
+            s[0] = omw * n[0] + omega * feq0 - (T)(w0 / T0d) * trP;
         }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int a = pair_rep(p), b = opp(a);
             const int c1 = cx(a), c2 = cy(a);
             const double w = weight<Q>(a);
-            const T phib = tb(TB::PHIB(p));
-            const T feqA = m * (Ev[p] + Od[p]) + dm * phib;
-            const T feqB = m * (Ev[p] - Od[p]) + dm * phib;
-            const T odd = (T)(w / T0d) * ((T)c1 * JF1 + (T)c2 * JF2);
-            const T even = (T)(w / T0d) * (((T)(c1 * c1) * P11 + (T)(c1 * c2) * P12s + (T)(c2 * c2) * P22) *
-                                               (T)(1.0 / T0d) -
-                                           trP);
-            s[a] = n[a] - omega * (n[a] - feqA) + even + odd;
-            s[b] = n[b] - omega * (n[b] - feqB) + even - odd;
+            const T mo = mO[p], cut = cUt[p];
+            const T E = tb(TB::D(p)) + (T)(w / (2.0 * T0d * T0d)) * (cut * cut - uuT);
+            const T base = m * E + dm * tb(TB::PHIB(p));
+            const T feqA = base + mo;
+            const T feqB = base - mo;
+            const T even = (T)(w * c1 * c1 / (T0d * T0d)) * P11 + (T)(w * c1 * c2 / (T0d * T0d)) * P12 +
+                           (T)(w * c2 * c2 / (T0d * T0d)) * P22 - (T)(w / T0d) * trP;
+            const T odd = (T)(w * c1 / T0d) * JF1 + (T)(w * c2 / T0d) * JF2;
+            s[a] = omw * n[a] + (omega * feqA + (even + odd));
+            s[b] = omw * n[b] + (omega * feqB + (even - odd));
         }
         if (it >= iters) break;
     }
@@ -362,9 +420,20 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
         mo[3 * nc + c] = (double)Ut1;
         mo[4 * nc + c] = (double)Ut2;
     } else {
-        const __amdgpu_buffer_rsrc_t rout = make_rsrc(d->P[pin ^ 1], pbytes);
+        const __amdgpu_buffer_rsrc_t rout = make_rsrc(d->P[pin ^ 1], (uint32_t)(plane * Q) * ES);
+        T Lx1 = 0, Lx2 = 0;
 #pragma unroll
-        for (int a = 0; a < Q; ++a) bstore<S, T>(rout, jb, (uint32_t)a * plane_b + (uint32_t)i * pitch_b, s[a]);
+        for (int a = 0; a < Q; ++a) {
+            const T v = pdec<Q, S, T>(penc<Q, S, T>(s[a], a), a);   // the value as stored
+            pstore<Q, S, T>(rout, jb, (uint32_t)a * plane_b + (uint32_t)i * pitch_b, a, s[a]);
+            if (a > 0) {
+                Lx1 += tb(TB::A1(a)) * v;
+                Lx2 += tb(TB::A2(a)) * v;
+            }
+        }
+        const __amdgpu_buffer_rsrc_t rlago = make_rsrc(d->lag[pin ^ 1], 2 * lplane_b);
+        bstore<T, T>(rlago, jt, rowt, Lx1);
+        bstore<T, T>(rlago, jt, lplane_b + rowt, Lx2);
         // side state of the moving walls: m and Ut^2 of the rows a wall pulls from
         T *side_out = (T *)d->side[pin ^ 1];
         if (bclo == BC_MOVING && i < hw) {

@@ -39,6 +39,7 @@ struct lbm_grid {
     // device buffers
     void *P[2] = {nullptr, nullptr};
     void *side[2] = {nullptr, nullptr};
+    void *lag[2] = {nullptr, nullptr};
     void *tab = nullptr;
     double *base = nullptr, *mB64 = nullptr;
     double *X = nullptr, *Y = nullptr;
@@ -61,6 +62,9 @@ struct lbm_grid {
 struct lbm_batch {
     std::vector<lbm_grid *> grids;
     hipStream_t stream = nullptr;
+    std::vector<hipStream_t> others;   // distinct grid streams other than `stream`
+    hipEvent_t ev = nullptr;
+    double *d_res = nullptr;           // [grids][RED_NF] reduction results
     struct Group {
         int q = 0, precision = 0, cell = 0;
         InstDesc *d_inst = nullptr;
@@ -115,7 +119,10 @@ static void dfree(lbm_grid *g, void *p)
     else (void)hipFree(p);
 }
 
-static size_t store_size(int precision) { return precision == LBM_FP64 ? sizeof(double) : sizeof(float); }
+static size_t store_size(int precision)
+{
+    return precision == LBM_FP64 ? sizeof(double) : (precision == LBM_FP16 ? 2 : sizeof(float));
+}
 static size_t comp_size(int precision) { return precision == LBM_FP64 ? sizeof(double) : sizeof(float); }
 
 static dim3 cell_grid(int n1, int n2) { return dim3((n2 + 127) / 128, n1); }
@@ -129,6 +136,10 @@ static StepFn step_fn(int precision, int cell, int mom)
     if (precision == LBM_FP64) {
         if (cell) return mom ? k_step<Q, double, double, true, true> : k_step<Q, double, double, true, false>;
         return mom ? k_step<Q, double, double, false, true> : k_step<Q, double, double, false, false>;
+    }
+    if (precision == LBM_FP16) {
+        if (cell) return mom ? k_step<Q, float, _Float16, true, true> : k_step<Q, float, _Float16, true, false>;
+        return mom ? k_step<Q, float, _Float16, false, true> : k_step<Q, float, _Float16, false, false>;
     }
     if (cell) return mom ? k_step<Q, float, float, true, true> : k_step<Q, float, float, true, false>;
     return mom ? k_step<Q, float, float, false, true> : k_step<Q, float, float, false, false>;
@@ -254,7 +265,8 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     for (int b : {D.bc_lo, D.bc_hi})
         if (b != LBM_PERIODIC && b != LBM_NOSLIP && b != LBM_MOVING) return fail(nullptr, LBM_EINVAL, "unknown boundary kind");
     if (D.n1 < cm) return fail(nullptr, LBM_EINVAL, "n1 must be at least c_max");
-    if (D.precision != LBM_FP64 && D.precision != LBM_FP32) return fail(nullptr, LBM_EINVAL, "unknown precision");
+    if (D.precision != LBM_FP64 && D.precision != LBM_FP32 && D.precision != LBM_FP16)
+        return fail(nullptr, LBM_EINVAL, "unknown precision");
     if (D.iterations < 0 || D.iterations > 16) return fail(nullptr, LBM_EINVAL, "iterations must be in 0..16");
     if ((int64_t)D.n1 * D.n2 > (int64_t)1 << 30) return fail(nullptr, LBM_EINVAL, "grid too large");
     {   // one population buffer must stay below 2 GiB (32-bit buffer offsets)
@@ -371,6 +383,7 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     ta.bc_hi = D.bc_hi;
     ta.base_kind = (D.precision == LBM_FP64) ? 2 : D.offset_base;
     ta.rho0 = D.rho0;
+    ta.kpi = -(1.0 - 1.0 / (2.0 * D.tau));
     g->base = (double *)dalloc(g, (size_t)g->nent * q * 8);
     g->mB64 = (double *)dalloc(g, (size_t)g->nent * 8);
     const int tabw = q == 9 ? Tab<9>::STRIDE : Tab<21>::STRIDE;
@@ -397,7 +410,9 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     for (int b = 0; b < 2; ++b) {
         g->P[b] = dalloc(g, plane * q * store_size(g->precision));
         g->side[b] = dalloc(g, (size_t)4 * g->hw * g->pitch * comp_size(g->precision));
-        if (!g->P[b] || !g->side[b]) return bail(LBM_ENOMEM, "device allocation failed (populations)");
+        g->lag[b] = dalloc(g, 2 * plane * comp_size(g->precision));
+        if (!g->P[b] || !g->side[b] || !g->lag[b]) return bail(LBM_ENOMEM, "device allocation failed (populations)");
+        HIPB(hipMemsetAsync(g->lag[b], 0, 2 * plane * comp_size(g->precision), st));
         HIPB(hipMemsetAsync(g->P[b], 0, plane * q * store_size(g->precision), st));
         HIPB(hipMemsetAsync(g->side[b], 0, (size_t)4 * g->hw * g->pitch * comp_size(g->precision), st));
     }
@@ -411,6 +426,8 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     I.P[1] = g->P[1];
     I.side[0] = g->side[0];
     I.side[1] = g->side[1];
+    I.lag[0] = g->lag[0];
+    I.lag[1] = g->lag[1];
     I.tab = g->tab;
     I.mom = g->mom;
     I.mB64 = g->mB64;
@@ -465,6 +482,53 @@ int lbm_set_launch(lbm_grid *g, int32_t wpb)
     return build_tiles(g);
 }
 
+namespace {
+// process-wide autotuner cache: (q, precision, cell tables, n1, n2) -> waves per block
+std::map<std::tuple<int, int, int, int, int>, int> g_tuned;
+} // namespace
+
+int lbm_autotune(lbm_grid *g, int32_t steps)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    if (steps < 2) steps = 2;
+    const auto key = std::make_tuple(g->q, g->precision, g->row ? 0 : 1, g->n1, g->n2);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+        const int rc = lbm_set_launch(g, it->second);
+        return rc != LBM_OK ? rc : it->second;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(g, hipEventCreate(&e0));
+    HIPCHK(g, hipEventCreate(&e1));
+    int best = 4;
+    float best_ms = 1e30f;
+    for (int w : {4, 2, 1}) {
+        int rc = lbm_set_launch(g, w);
+        for (int s = 0; rc == LBM_OK && s < 2; ++s) rc = launch_step(g, s & 1, 0);
+        HIPCHK(g, hipEventRecord(e0, g->stream));
+        for (int s = 0; rc == LBM_OK && s < steps; ++s) rc = launch_step(g, s & 1, 0);
+        HIPCHK(g, hipEventRecord(e1, g->stream));
+        HIPCHK(g, hipEventSynchronize(e1));
+        if (rc != LBM_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
+        float ms = 0.f;
+        HIPCHK(g, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = w;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_tuned[key] = best;
+    g->inited = false;   // the timing steps ran on whatever state the grid held
+    const int rc = lbm_set_launch(g, best);
+    return rc != LBM_OK ? rc : best;
+}
+
 int lbm_set_volume(lbm_grid *g, const double *J)
 {
     if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
@@ -481,6 +545,22 @@ int lbm_set_volume(lbm_grid *g, const double *J)
 
 static int reduce(lbm_grid *g, int update_snap, double out[RED_NF]);
 
+static int form_lag(lbm_grid *g, int pin)
+{
+    const dim3 gr = cell_grid(g->n1, g->n2);
+    if (g->q == 9) {
+        if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_lag<9, double, double>), gr, dim3(128), 0, g->stream, g->d_inst, pin);
+        else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_lag<9, float, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, pin);
+        else hipLaunchKernelGGL((k_lag<9, float, float>), gr, dim3(128), 0, g->stream, g->d_inst, pin);
+    } else {
+        if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_lag<21, double, double>), gr, dim3(128), 0, g->stream, g->d_inst, pin);
+        else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_lag<21, float, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, pin);
+        else hipLaunchKernelGGL((k_lag<21, float, float>), gr, dim3(128), 0, g->stream, g->d_inst, pin);
+    }
+    HIPCHK(g, hipGetLastError());
+    return LBM_OK;
+}
+
 int lbm_init(lbm_grid *g, const double *u0)
 {
     if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
@@ -496,12 +576,18 @@ int lbm_init(lbm_grid *g, const double *u0)
     const dim3 gr = cell_grid(g->n1, g->n2);
     if (g->q == 9) {
         if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_init<9, double, double>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
+        else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_init<9, float, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
         else hipLaunchKernelGGL((k_init<9, float, float>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
     } else {
         if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_init<21, double, double>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
+        else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_init<21, float, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
         else hipLaunchKernelGGL((k_init<21, float, float>), gr, dim3(128), 0, g->stream, g->d_inst, ia);
     }
     HIPCHK(g, hipGetLastError());
+    {
+        const int rc = form_lag(g, 0);
+        if (rc != LBM_OK) return rc;
+    }
     HIPCHK(g, hipStreamSynchronize(g->stream));
     if (du) dfree(g, du);
     g->inited = true;
@@ -562,26 +648,29 @@ int lbm_step(lbm_grid *g, int64_t n)
 
 static int run_moments(lbm_grid *g) { return launch_step(g, g->par, 1); }
 
-static int reduce(lbm_grid *g, int update_snap, double out[RED_NF])
+static int launch_reduce(lbm_grid *g, int update_snap, double *dst)
 {
     int rc = run_moments(g);
     if (rc != LBM_OK) return rc;
     ReduceArgs ra{g->mom, g->snap, g->g4, g->xc, g->yc, g->ncell, update_snap, g->partial};
     hipLaunchKernelGGL(k_reduce, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, g->stream, ra);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, g->stream, (const double *)g->partial, g->redout);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, g->stream, (const double *)g->partial, dst);
     HIPCHK(g, hipGetLastError());
+    return LBM_OK;
+}
+
+static int reduce(lbm_grid *g, int update_snap, double out[RED_NF])
+{
+    int rc = launch_reduce(g, update_snap, g->redout);
+    if (rc != LBM_OK) return rc;
     HIPCHK(g, hipMemcpyAsync(out, g->redout, RED_NF * 8, hipMemcpyDeviceToHost, g->stream));
     HIPCHK(g, hipStreamSynchronize(g->stream));
     return LBM_OK;
 }
 
-int lbm_residual(lbm_grid *g, lbm_resid *out)
+// residual record from the reduced sums; advances the residual reference
+static int fill_resid(lbm_grid *g, const double r[RED_NF], lbm_resid *out)
 {
-    if (!g || !out) return fail(g, LBM_EINVAL, "null argument");
-    if (!g->inited) return fail(g, LBM_ESTATE, "lbm_init must be called first");
-    double r[RED_NF];
-    int rc = reduce(g, 1, r);
-    if (rc != LBM_OK) return rc;
     const int64_t K = g->step - g->snap_step;
     out->step = g->step;
     out->mass = r[0];
@@ -595,6 +684,16 @@ int lbm_residual(lbm_grid *g, lbm_resid *out)
     g->snap_step = g->step;
     if (out->bad_cells > 0) return fail(g, LBM_EUNSTABLE, "non-finite values or m <= 0 in some cells");
     return LBM_OK;
+}
+
+int lbm_residual(lbm_grid *g, lbm_resid *out)
+{
+    if (!g || !out) return fail(g, LBM_EINVAL, "null argument");
+    if (!g->inited) return fail(g, LBM_ESTATE, "lbm_init must be called first");
+    double r[RED_NF];
+    int rc = reduce(g, 1, r);
+    if (rc != LBM_OK) return rc;
+    return fill_resid(g, r, out);
 }
 
 int lbm_moments(lbm_grid *g, double *m, double *U, double *Ut)
@@ -664,9 +763,11 @@ int lbm_get_state(lbm_grid *g, double *P, double *side)
         if (!tmp) return fail(g, LBM_ENOMEM, "allocation failed");
         if (g->q == 9) {
             if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_out<9, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+            else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_state_out<9, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
             else hipLaunchKernelGGL((k_state_out<9, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
         } else {
             if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_out<21, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+            else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_state_out<21, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
             else hipLaunchKernelGGL((k_state_out<21, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
         }
         HIPCHK(g, hipGetLastError());
@@ -699,12 +800,16 @@ int lbm_set_state(lbm_grid *g, const double *P, const double *side)
         HIPCHK(g, hipMemcpyAsync(tmp, P, (size_t)g->ncell * g->q * 8, hipMemcpyHostToDevice, g->stream));
         if (g->q == 9) {
             if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_in<9, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+            else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_state_in<9, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
             else hipLaunchKernelGGL((k_state_in<9, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
         } else {
             if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_in<21, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
+            else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_state_in<21, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
             else hipLaunchKernelGGL((k_state_in<21, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
         }
         HIPCHK(g, hipGetLastError());
+        const int rc = form_lag(g, g->par);
+        if (rc != LBM_OK) return rc;
         HIPCHK(g, hipStreamSynchronize(g->stream));
         dfree(g, tmp);
     }
@@ -802,6 +907,7 @@ void lbm_batch_destroy(lbm_batch *b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
     for (void *p : b->allocs) (void)hipFree(p);
+    if (b->ev) (void)hipEventDestroy(b->ev);
     delete b;
 }
 
@@ -818,10 +924,8 @@ int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
             delete b;
             return fail(nullptr, LBM_ESTATE, "every grid of a batch must be initialised");
         }
-        if (g->stream != b->stream) {
-            delete b;
-            return fail(nullptr, LBM_EINVAL, "grids of a batch must share one stream");
-        }
+        if (g->stream != b->stream && std::find(b->others.begin(), b->others.end(), g->stream) == b->others.end())
+            b->others.push_back(g->stream);
         b->grids.push_back(g);
         groups[std::make_tuple(g->q, g->precision, g->row ? 0 : 1)].push_back(k);
     }
@@ -863,7 +967,31 @@ int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
         G.ntiles = (int)ord.size();
         b->groups.push_back(G);
     }
+    if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) {
+        lbm_batch_destroy(b);
+        return fail(nullptr, LBM_EDEVICE, "event creation failed");
+    }
     *out = b;
+    return LBM_OK;
+}
+
+// grids on other streams: the batch stream waits for their pending work before
+// stepping, and they wait for the batch's steps afterwards
+static int batch_join_in(lbm_batch *b)
+{
+    for (hipStream_t s : b->others) {
+        if (hipEventRecord(b->ev, s) != hipSuccess || hipStreamWaitEvent(b->stream, b->ev, 0) != hipSuccess)
+            return fail(nullptr, LBM_EDEVICE, "stream join failed");
+    }
+    return LBM_OK;
+}
+
+static int batch_join_out(lbm_batch *b)
+{
+    if (b->others.empty()) return LBM_OK;
+    if (hipEventRecord(b->ev, b->stream) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "event record failed");
+    for (hipStream_t s : b->others)
+        if (hipStreamWaitEvent(s, b->ev, 0) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "stream join failed");
     return LBM_OK;
 }
 
@@ -883,6 +1011,10 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
     if (!b || n < 0) return fail(nullptr, LBM_EINVAL, "bad batch step arguments");
     const int GS = 16;
     int64_t left = n;
+    {
+        const int rc = batch_join_in(b);
+        if (rc != LBM_OK) return rc;
+    }
     // the batch's own parity: step s of the batch uses par = s & 1
     if (left >= GS && (b->step & 1) == 0) {
         if (!b->graph.exec) {
@@ -911,7 +1043,33 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
         g->par ^= (int)(n & 1);
         g->step += n;
     }
-    return LBM_OK;
+    return batch_join_out(b);
+}
+
+int lbm_batch_residuals(lbm_batch *b, lbm_resid *out)
+{
+    if (!b || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    const size_t n = b->grids.size();
+    if (!b->d_res) {
+        if (hipMalloc((void **)&b->d_res, n * RED_NF * 8) != hipSuccess) return fail(nullptr, LBM_ENOMEM, "allocation failed");
+        b->allocs.push_back(b->d_res);
+    }
+    for (size_t k = 0; k < n; ++k) {
+        const int rc = launch_reduce(b->grids[k], 1, b->d_res + k * RED_NF);
+        if (rc != LBM_OK) return rc;
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "sync failed");
+    for (hipStream_t s : b->others)
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "sync failed");
+    std::vector<double> h(n * RED_NF);
+    if (hipMemcpy(h.data(), b->d_res, n * RED_NF * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(nullptr, LBM_EDEVICE, "copy failed");
+    int first = LBM_OK;
+    for (size_t k = 0; k < n; ++k) {
+        const int rc = fill_resid(b->grids[k], h.data() + k * RED_NF, out + k);
+        if (rc != LBM_OK && first == LBM_OK) first = rc;
+    }
+    return first;
 }
 
 int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *precision, int64_t *cells)

@@ -118,6 +118,7 @@ struct TableArgs {
     int n1, n2, ncell, cellmode, nent;
     int periodic1, bc_lo, bc_hi, base_kind;
     double rho0;
+    double kpi;           // -(1 - 1/(2 tau))
 };
 
 __host__ __device__ inline int entry_cell(const TableArgs &t, int e) { return t.cellmode ? e : e * t.n2; }
@@ -206,6 +207,10 @@ __global__ void k_table(TableArgs t, const double *__restrict__ base, const doub
         put(TB::K(p), weight<Q>(a) * (cGc - T0 * (G11 + G22)) / (2.0 * T0 * T0));
         put(TB::D(p), rest_phi<Q>(a, G11, G12, G22) - phiB(a));
         put(TB::PHIB(p), phiB(a));
+        const double S1 = A(a, 0) + A(opp(a), 0), S2 = A(a, 1) + A(opp(a), 1);
+        put(TB::X11(p), t.kpi * c1 * S1);
+        put(TB::X12(p), t.kpi * (c1 * S2 + c2 * S1));
+        put(TB::X22(p), t.kpi * c2 * S2);
     }
 }
 
@@ -262,7 +267,7 @@ __global__ void k_init(const InstDesc *__restrict__ dd, InitArgs ia)
     S *P = (S *)d->P[ia.pin];
     for (int a = 0; a < Q; ++a) {
         const double N = m * feq_phi<Q>(a, U, U, G11, G12, G22);
-        P[(size_t)a * d->plane + (size_t)i * d->pitch + j] = (S)(N - ia.base[(size_t)e * Q + a]);
+        P[(size_t)a * d->plane + (size_t)i * d->pitch + j] = penc<Q, S, double>(N - ia.base[(size_t)e * Q + a], a);
     }
     T *side = (T *)d->side[ia.pin];
     const int hw = d->hw;
@@ -275,6 +280,31 @@ __global__ void k_init(const InstDesc *__restrict__ dd, InitArgs ia)
         side[((size_t)2 * hw + k) * d->pitch + j] = (T)m;
         side[((size_t)3 * hw + k) * d->pitch + j] = (T)U[1];
     }
+}
+
+// lagged own-cell force sums sum_a A+^i_a s_a of a stored state (after
+// initialisation or a state upload), exactly as the step kernel forms them
+template <int Q, typename T, typename S>
+__global__ void k_lag(const InstDesc *__restrict__ d, int pin)
+{
+    using TB = Tab<Q>;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= d->n2 || i >= d->n1) return;
+    const int c = i * d->n2 + j;
+    const T *tab = (const T *)d->tab;
+    auto tv = [&](int f) { return d->cell ? tab[(size_t)f * d->ncell + c] : tab[(size_t)i * TB::STRIDE + f]; };
+    const S *P = (const S *)d->P[pin];
+    const size_t off = (size_t)i * d->pitch + j;
+    T L1 = 0, L2 = 0;
+    for (int a = 1; a < Q; ++a) {
+        const T v = pdec<Q, S, T>(P[(size_t)a * d->plane + off], a);
+        L1 += tv(TB::A1(a)) * v;
+        L2 += tv(TB::A2(a)) * v;
+    }
+    T *lag = (T *)d->lag[pin];
+    lag[off] = L1;
+    lag[(size_t)d->plane + off] = L2;
 }
 
 // ---------------------------------------------------------------------------
@@ -290,7 +320,8 @@ __global__ void k_state_out(const InstDesc *__restrict__ d, const double *__rest
     const int c = i * d->n2 + j, e = cellmode ? c : i;
     const S *P = (const S *)d->P[pin];
     for (int a = 0; a < Q; ++a)
-        out[(size_t)a * d->ncell + c] = base[(size_t)e * Q + a] + (double)P[(size_t)a * d->plane + (size_t)i * d->pitch + j];
+        out[(size_t)a * d->ncell + c] =
+            base[(size_t)e * Q + a] + pdec<Q, S, double>(P[(size_t)a * d->plane + (size_t)i * d->pitch + j], a);
 }
 
 template <int Q, typename S>
@@ -303,7 +334,8 @@ __global__ void k_state_in(const InstDesc *__restrict__ d, const double *__restr
     const int c = i * d->n2 + j, e = cellmode ? c : i;
     S *P = (S *)d->P[pin];
     for (int a = 0; a < Q; ++a)
-        P[(size_t)a * d->plane + (size_t)i * d->pitch + j] = (S)(in[(size_t)a * d->ncell + c] - base[(size_t)e * Q + a]);
+        P[(size_t)a * d->plane + (size_t)i * d->pitch + j] =
+            penc<Q, S, double>(in[(size_t)a * d->ncell + c] - base[(size_t)e * Q + a], a);
 }
 
 // side state [2][2][hw][pitch] (compute type) <-> [2][2][hw][n2] FP64

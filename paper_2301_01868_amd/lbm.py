@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_PERIODIC, LBM_NOSLIP, LBM_MOVING = 0, 1, 2
-LBM_FP64, LBM_FP32 = 0, 1
+LBM_FP64, LBM_FP32, LBM_FP16 = 0, 1, 2
 LBM_BASE_LOCAL_REST, LBM_BASE_W_RHO0, LBM_BASE_NONE = 0, 1, 2
 LBM_GEOM_AUTO, LBM_GEOM_CELL = 0, 1
 BC = {"periodic": LBM_PERIODIC, "noslip": LBM_NOSLIP, "moving": LBM_MOVING}
@@ -24,7 +24,7 @@ BC = {"periodic": LBM_PERIODIC, "noslip": LBM_NOSLIP, "moving": LBM_MOVING}
 EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_error", "lbm_grid_info_get",
             "lbm_set_volume", "lbm_get_volume", "lbm_init", "lbm_step", "lbm_moments", "lbm_residual", "lbm_noflow_adjust",
             "lbm_get_state", "lbm_set_state", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
-            "lbm_stream", "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch",
+            "lbm_stream", "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_autotune",
             "lbm_copy_probe"]
 
 
@@ -101,9 +101,11 @@ def load():
     L.lbm_batch_step.argtypes = [vp, ct.c_int64]
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_destroy.restype = None
+    L.lbm_batch_residuals.argtypes = [vp, ct.POINTER(lbm_resid)]
     L.lbm_batch_info.argtypes = [vp, ct.c_int32, I32, I32, ct.POINTER(ct.c_int64)]
     L.lbm_batch_step_group.argtypes = [vp, ct.c_int32, ct.c_int64]
     L.lbm_set_launch.argtypes = [vp, ct.c_int32]
+    L.lbm_autotune.argtypes = [vp, ct.c_int32]
     L.lbm_copy_probe.argtypes = [vp, vp, ct.c_size_t, vp]
     _lib = L
     return L
@@ -242,6 +244,13 @@ def lbm_stream(h):
     return load().lbm_stream(h)
 
 
+def lbm_autotune(h, steps=20):
+    rc = load().lbm_autotune(h, int(steps))
+    if rc < 0:
+        _chk(rc, h)
+    return rc
+
+
 def lbm_set_launch(h, waves_per_block):
     _chk(load().lbm_set_launch(h, int(waves_per_block)), h)
 
@@ -259,6 +268,16 @@ def lbm_batch_step(b, n):
 
 def lbm_batch_destroy(b):
     load().lbm_batch_destroy(b)
+
+
+def lbm_batch_residuals(b, n, check=False):
+    arr = (lbm_resid * n)()
+    rc = load().lbm_batch_residuals(b, arr)
+    if check:
+        _chk(rc)
+    elif rc not in (LBM_OK, LBM_EUNSTABLE):
+        _chk(rc)
+    return list(arr)
 
 
 def lbm_batch_info(b, group):
@@ -351,6 +370,9 @@ class Grid:
 
     def set_launch(self, wpb):
         lbm_set_launch(self.h, wpb)
+
+    def autotune(self, steps=20):
+        return lbm_autotune(self.h, steps)
 
     @property
     def stream(self):

@@ -115,6 +115,26 @@ def test_fp32_velocity_within_tolerance(name, case):
     assert norm_rel(m, mo) <= 1e-6
 
 
+@pytest.mark.parametrize("name,case", CASES, ids=[c[0] for c in CASES])
+def test_fp16_velocity_error_stated(name, case):
+    """FP16 storage (per-direction scaled offsets, FP32 arithmetic): the error
+    against the FP64 oracle is measured and reported (an 11-bit mantissa on
+    the stored offsets); it must stay within 2e-2 of the characteristic speed."""
+    steps = 2000 if name.startswith("couette_q9") else 300
+    g, o = pair(case, precision=lbm.LBM_FP16)
+    g.step(steps)
+    o.step(steps)
+    m, U, Ut = g.moments()
+    mo, Uo, Uto = o.moments()
+    geo = o.geometry()
+    u = Ut[:, :1] * geo["g1"] + Ut[:, 1:] * geo["g2"]
+    uo = Uto[:, :1] * geo["g1"] + Uto[:, 1:] * geo["g2"]
+    Uc = characteristic_speed(case, uo)
+    err = np.abs(u - uo).max() / Uc
+    say(name, "fp16 velocity err / U", err)
+    assert err <= 2e-2
+
+
 def test_moments_residual_and_mass():
     case = G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, tau=0.8)
     g, o = pair(case)
