@@ -50,14 +50,15 @@ def cpu_baseline(case, target_s=15.0):
     o.step(1, threads)
     t1 = time.perf_counter()
     per = max(t1 - t0, 1e-6)
-    k = max(1, min(2000, int(target_s / per)))
+    k = max(1, min(200000, int(target_s / per)))
     t0 = time.perf_counter()
     o.step(k, threads)
     dt = time.perf_counter() - t0
     lups = case.ncell * k / dt
     return {"value": lups / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": "%s, %d steps of the full %dx%d grid, FP64, %d OpenMP threads, %.1f s"
-                      % (case.meta.get("workload", "grid"), k, case.n1, case.n2, threads, dt)}
+            "sample": "%s: %d steps of the full %dx%d D2Q%d grid, FP64, %d OpenMP threads, %.1f s"
+                      % (case.meta.get("workload", case.meta.get("problem", "grid")), k, case.n1, case.n2, case.q,
+                         threads, dt)}
 
 
 def measure(cases, prec, steps, warmup, wpb=0, stream=None):
@@ -184,8 +185,20 @@ def main():
             ev1.record(stream)
         torch.cuda.synchronize()
         ms_t = ev0.elapsed_time(ev1) / reps
-        print(json.dumps({"copy_probe_bytes": nbytes, "k_copy_GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1),
-                          "torch_copy_GBps": round(2 * nbytes / (ms_t * 1e-3) / 1e9, 1)}), flush=True)
+        res = {"copy_probe_bytes": nbytes, "k_copy_GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1),
+               "torch_copy_GBps": round(2 * nbytes / (ms_t * 1e-3) / 1e9, 1)}
+        sink = torch.empty(8 << 20, dtype=torch.float32, device="cuda")
+        for kind, name, mult in ((0, "nt_copy_GBps", 2), (1, "nt_read_GBps", 1), (2, "nt_write_GBps", 1)):
+            d_ptr = sink.data_ptr() if kind == 1 else dst.data_ptr()
+            lbm.lbm_bandwidth_probe(d_ptr, src.data_ptr(), nbytes, kind, ct_stream(stream))
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(reps):
+                lbm.lbm_bandwidth_probe(d_ptr, src.data_ptr(), nbytes, kind, ct_stream(stream))
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            res[name] = round(mult * nbytes / (ev0.elapsed_time(ev1) / reps * 1e-3) / 1e9, 1)
+        print(json.dumps(res), flush=True)
         return
     if args.serve:
         serve_bench(args)
@@ -202,8 +215,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        q21 = [c for c in cases if c.q == 21] or cases
-        cpu = cpu_baseline(min(q21, key=lambda c: c.ncell))
+        q21 = sorted([c for c in cases if c.q == 21] or cases, key=lambda c: c.ncell)
+        cpu = cpu_baseline(q21[len(q21) // 2])    # the median-sized D2Q21 grid of the workload
 
     out = {
         "metric": "MLUPS + % HBM roofline (D2Q21 FP32 vs FP64)",

@@ -228,8 +228,14 @@ int lbm_set_launch(lbm_grid *g, int32_t waves_per_block);
  * (> 0) or an error code. */
 int lbm_autotune(lbm_grid *g, int32_t steps);
 
-/* Plain device copy kernel (for calibrating memory-traffic counters). */
+/* Plain device copy kernel (for calibrating memory-traffic counters): copies
+ * `bytes` (a multiple of 16) from src to dst on `stream`. */
 int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Bandwidth probes with non-temporal 16-byte accesses: kind 0 copies src to
+ * dst, kind 1 reads src (dst receives 8192 * 256 * 16 bytes of xor sums, so it
+ * must hold at least 32 MiB), kind 2 fills dst. */
+int lbm_bandwidth_probe(void *dst, const void *src, size_t bytes, int32_t kind, void *stream);
 
 #ifdef __cplusplus
 }

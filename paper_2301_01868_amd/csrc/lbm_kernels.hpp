@@ -126,13 +126,22 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t by
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
+// Cache policy of the population and force-sum accesses: non-temporal (nt)
+// loads and stores (each value is touched once per step; measured faster
+// than the default policy on gfx950).
+#ifndef LBM_LD_AUX
+#define LBM_LD_AUX 2
+#endif
+#ifndef LBM_ST_AUX
+#define LBM_ST_AUX 2
+#endif
 template <typename S, typename T>
 __device__ inline T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
     if constexpr (sizeof(S) == 8) {
-        return (T)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        return (T)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, LBM_LD_AUX));
     } else {
-        return (T)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        return (T)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LBM_LD_AUX));
     }
 }
 template <typename S, typename T>
@@ -140,9 +149,9 @@ __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t 
 {
     if constexpr (sizeof(S) == 8) {
         using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, (double)v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, (double)v), r, voff, soff, LBM_ST_AUX);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, (float)v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, (float)v), r, voff, soff, LBM_ST_AUX);
     }
 }
 
@@ -160,7 +169,7 @@ template <int Q, typename S, typename T>
 __device__ inline T pload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, int a)
 {
     if constexpr (sizeof(S) == 2) {
-        const _Float16 h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+        const _Float16 h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LD_AUX));
         return (T)h * (T)plane_scale<Q, S>(a);
     } else {
         return bload<S, T>(r, voff, soff);
@@ -183,7 +192,7 @@ __device__ inline void pstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t 
 {
     if constexpr (sizeof(S) == 2) {
         using U16 = decltype(__builtin_amdgcn_raw_buffer_load_b16(r, 0, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(U16, penc<Q, S, T>(v, a)), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(U16, penc<Q, S, T>(v, a)), r, voff, soff, LBM_ST_AUX);
     } else {
         bstore<S, T>(r, voff, soff, v);
     }

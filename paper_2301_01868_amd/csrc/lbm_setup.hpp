@@ -457,4 +457,26 @@ __global__ void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, s
         dst[k] = src[k];
 }
 
+// bandwidth probes: non-temporal copy, read-only (xor into one value per
+// thread), write-only (fill)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void k_copy_nt(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n16)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
+}
+__global__ void k_read_nt(const u32x4 *__restrict__ src, u32x4 *__restrict__ sink, size_t n16)
+{
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
+        acc ^= __builtin_nontemporal_load(src + k);
+    sink[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+__global__ void k_write_nt(u32x4 *__restrict__ dst, size_t n16)
+{
+    const u32x4 v = {1u, 2u, 3u, 4u};
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(v, dst + k);
+}
+
 } // namespace lbm

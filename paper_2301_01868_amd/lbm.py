@@ -25,7 +25,7 @@ EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_erro
             "lbm_set_volume", "lbm_get_volume", "lbm_init", "lbm_step", "lbm_moments", "lbm_residual", "lbm_noflow_adjust",
             "lbm_get_state", "lbm_set_state", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
             "lbm_stream", "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_autotune",
-            "lbm_copy_probe"]
+            "lbm_copy_probe", "lbm_bandwidth_probe"]
 
 
 class LbmError(RuntimeError):
@@ -107,6 +107,7 @@ def load():
     L.lbm_set_launch.argtypes = [vp, ct.c_int32]
     L.lbm_autotune.argtypes = [vp, ct.c_int32]
     L.lbm_copy_probe.argtypes = [vp, vp, ct.c_size_t, vp]
+    L.lbm_bandwidth_probe.argtypes = [vp, vp, ct.c_size_t, ct.c_int32, vp]
     _lib = L
     return L
 
@@ -299,6 +300,10 @@ def lbm_batch_groups(b):
 
 def lbm_batch_step_group(b, group, n):
     _chk(load().lbm_batch_step_group(b, int(group), int(n)))
+
+
+def lbm_bandwidth_probe(dst_ptr, src_ptr, nbytes, kind, stream=None):
+    _chk(load().lbm_bandwidth_probe(ct.c_void_p(dst_ptr), ct.c_void_p(src_ptr), int(nbytes), int(kind), stream))
 
 
 def lbm_copy_probe(dst_ptr, src_ptr, nbytes, stream=None):
