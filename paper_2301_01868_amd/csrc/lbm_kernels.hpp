@@ -67,13 +67,15 @@ struct Tab {
 
 // Per-instance launch descriptor (device memory, read with scalar loads).
 struct InstDesc {
-    void *P[2];          // population storage buffers, [Q][n1][pitch]
+    void *P[2];          // population storage buffers, [n1][Q][pitch] (strides sa, sr)
     void *side[2];       // moving-wall side state, [2 walls][2 fields][hw][pitch]
-    void *lag[2];        // lagged own-cell force sums sum_a A+^i_a s_a, [2][n1][pitch] (compute type)
+    void *lag[2];        // lagged own-cell force sums sum_a A+^i_a s_a, [n1][2][pitch] (compute type)
     const void *tab;     // step table
     double *mom;         // moments output [5][ncell] (m, U1, U2, Ut1, Ut2)
     const double *mB64;  // FP64 base mass per table entry
-    long long plane;     // elements per population plane (n1 * pitch)
+    long long plane;     // n1 * pitch: a population buffer holds Q * plane elements, a lag buffer 2 * plane
+    long long sa, sr;    // element strides between directions and between rows of a population buffer
+    long long lsa, lsr;  // the same for the two force-sum fields of a lag buffer
     int n1, n2, pitch, hw;
     int periodic1, bc_lo, bc_hi, cell;
     int iters, ncell, par0, pad;
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
     }
 
     constexpr uint32_t ES = sizeof(S);
-    const uint32_t plane_b = (uint32_t)plane * ES, pitch_b = (uint32_t)pitch * ES;
+    const uint32_t sa_b = (uint32_t)d->sa * ES, sr_b = (uint32_t)d->sr * ES;
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(d->P[pin], (uint32_t)(plane * Q) * ES);
     const uint32_t jb = (uint32_t)j * ES;
 
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
         // same direction; the column shift rides in the scalar offset
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
-            const uint32_t soff = (uint32_t)((int)(a * plane_b + (i - cx(a)) * pitch_b) - cy(a) * (int)ES);
+            const uint32_t soff = (uint32_t)((int)(a * sa_b + (i - cx(a)) * sr_b) - cy(a) * (int)ES);
             n[a] = pload<Q, S, T>(rin, jb, soff, a);
             if (a > 0) n[a] += tb(TB::DB(a));
         }
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
             int r, beta, wall;
             pull_source(i, a, n1, per1, bclo, bchi, r, beta, wall);
             const uint32_t cb = colb[c2 + CM];
-            T v = pload<Q, S, T>(rin, cb, (uint32_t)beta * plane_b + (uint32_t)r * pitch_b, a);
+            T v = pload<Q, S, T>(rin, cb, (uint32_t)beta * sa_b + (uint32_t)r * sr_b, a);
             if (a > 0) v += tb(TB::DB(a));
             if (c2 != 0 && wall != 0) {
                 const int sd = wall - 1;
@@ -310,11 +312,11 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
     // lagged own-cell force sums sum_a A+^i_a s_a(q, t-1), formed when the
     // previous step produced N'(q, t-1)
     constexpr uint32_t ET = sizeof(T);
-    const uint32_t lplane_b = (uint32_t)plane * ET;
-    const __amdgpu_buffer_rsrc_t rlag = make_rsrc(d->lag[pin], 2 * lplane_b);
-    const uint32_t jt = (uint32_t)j * ET, rowt = (uint32_t)i * pitch * ET;
+    const uint32_t lag_bytes = 2 * (uint32_t)plane * ET, lsa_b = (uint32_t)d->lsa * ET;
+    const __amdgpu_buffer_rsrc_t rlag = make_rsrc(d->lag[pin], lag_bytes);
+    const uint32_t jt = (uint32_t)j * ET, rowt = (uint32_t)i * (uint32_t)d->lsr * ET;
     const T Lo1 = bload<T, T>(rlag, jt, rowt);
-    const T Lo2 = bload<T, T>(rlag, jt, lplane_b + rowt);
+    const T Lo2 = bload<T, T>(rlag, jt, lsa_b + rowt);
 
     // ---- moments (in +-c pairs) ----
     T dm = n[0], mU1 = 0, mU2 = 0;
@@ -462,15 +464,15 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
             const T v = pdec<Q, S, T>(penc<Q, S, T>(s[a], a), a);   // the value as stored
-            pstore<Q, S, T>(rout, jb, (uint32_t)a * plane_b + (uint32_t)i * pitch_b, a, s[a]);
+            pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + (uint32_t)i * sr_b, a, s[a]);
             if (a > 0) {
                 Lx1 += tb(TB::A1(a)) * v;
                 Lx2 += tb(TB::A2(a)) * v;
             }
         }
-        const __amdgpu_buffer_rsrc_t rlago = make_rsrc(d->lag[pin ^ 1], 2 * lplane_b);
+        const __amdgpu_buffer_rsrc_t rlago = make_rsrc(d->lag[pin ^ 1], lag_bytes);
         bstore<T, T>(rlago, jt, rowt, Lx1);
-        bstore<T, T>(rlago, jt, lplane_b + rowt, Lx2);
+        bstore<T, T>(rlago, jt, lsa_b + rowt, Lx2);
         // side state of the moving walls: m and Ut^2 of the rows a wall pulls from
         T *side_out = (T *)d->side[pin ^ 1];
         if (bclo == BC_MOVING && i < hw) {
