@@ -194,8 +194,10 @@ void *lbm_stream(lbm_grid *g);
 /* Many grids advanced together: one launch per lattice and precision per step
  * over a flattened table of row tiles; steps of a batch are captured in HIP
  * graphs and run on the stream of grids[0] (grids on other streams are joined
- * with events before and after).  Every grid must be initialised; while it is
- * in a batch a grid must only be stepped through the batch. */
+ * with events before and after).  Every grid must be initialised
+ * (LBM_ESTATE otherwise) and appear once (LBM_EINVAL otherwise); n > 0.
+ * The batch does not own the grids: destroy the batch before its grids.
+ * While it is in a batch a grid must only be stepped through the batch. */
 int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out);
 int lbm_batch_step(lbm_batch *b, int64_t n);
 void lbm_batch_destroy(lbm_batch *b);

@@ -935,6 +935,10 @@ int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
             delete b;
             return fail(nullptr, LBM_ESTATE, "every grid of a batch must be initialised");
         }
+        if (std::find(b->grids.begin(), b->grids.end(), g) != b->grids.end()) {
+            delete b;
+            return fail(nullptr, LBM_EINVAL, "a grid appears twice in the batch");
+        }
         if (g->stream != b->stream && std::find(b->others.begin(), b->others.end(), g->stream) == b->others.end())
             b->others.push_back(g->stream);
         b->grids.push_back(g);

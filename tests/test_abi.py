@@ -45,3 +45,44 @@ def test_bad_arguments_are_rejected(lib):
         lbm.Grid(case.replace(halo=2))
     with pytest.raises(lbm.LbmError):
         lbm.Grid(G.planar_couette(21, G.faces_uniform(2), n2=4))
+
+
+def _desc_case(**kw):
+    """A Case whose coordinate arrays are placeholders: every case built here
+    is rejected by the argument checks before the library reads them."""
+    from paper_2301_01868_amd import grids as G
+    return G.planar_couette(21, G.faces_uniform(8), n2=4).replace(**kw)
+
+
+@pytest.mark.parametrize("kw,what", [
+    (dict(n1=0), "empty along q1"),
+    (dict(n2=0), "empty along q2"),
+    (dict(q=15), "unknown lattice"),
+    (dict(n1=16384, n2=2048), "population buffer of 2 GiB or more"),
+    (dict(n1=1 << 16, n2=1 << 15), "more than 2^30 cells"),
+])
+def test_create_rejects_shapes(lib, kw, what):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Grid(_desc_case(**kw))
+    assert e.value.code == lbm.LBM_EINVAL, what
+
+
+def test_create_rejects_modes(lib):
+    case = _desc_case()
+    for kw in (dict(precision=7), dict(iterations=17), dict(iterations=-1)):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.Grid(case, **kw)
+        assert e.value.code == lbm.LBM_EINVAL, kw
+    # a periodic q1 side must be paired with a periodic one
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Grid(case.replace(bc_lo="periodic", bc_hi="noslip"))
+    assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_null_arguments_are_rejected(lib):
+    import ctypes as ct
+    h = ct.c_void_p()
+    assert lib.lbm_grid_create(None, ct.byref(h)) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_create(None, 1, ct.byref(h)) == lbm.LBM_EINVAL
+    assert lib.lbm_init(None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_step(None, ct.c_int64(1)) == lbm.LBM_EINVAL

@@ -85,3 +85,23 @@ def test_checkpoint_resume():
         err = np.abs(Pa - Pb).max() / np.abs(Pa).max()
         say("resume", prec, err)
         assert err <= max(tol, 1e-15 if prec == lbm.LBM_FP64 else 1e-7)
+
+
+def test_batch_rejects_repeated_or_uninitialised_grids():
+    case = G.planar_couette(21, G.faces_uniform(8), n2=70, u_wall=0.04, tau=0.8)
+    a = lbm.Grid(case, precision=lbm.LBM_FP32)
+    b = lbm.Grid(case, precision=lbm.LBM_FP32)
+    a.init()
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_batch_create([a.h, a.h])
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_batch_create([a.h, b.h])
+    assert e.value.code == lbm.LBM_ESTATE
+    b.init()
+    bt = lbm.lbm_batch_create([a.h, b.h])
+    lbm.lbm_batch_step(bt, 4)
+    lbm.lbm_batch_destroy(bt)
+    Pa, _ = a.get_state()
+    Pb, _ = b.get_state()
+    assert np.array_equal(Pa, Pb)
