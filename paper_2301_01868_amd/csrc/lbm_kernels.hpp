@@ -67,7 +67,7 @@ struct Tab {
 
 // Per-instance launch descriptor (device memory, read with scalar loads).
 struct InstDesc {
-    void *P[2];          // population storage buffers, [n1][Q][pitch] (strides sa, sr)
+    void *P[2];          // population storage buffers, [n1][blocks][Q][block width] (see pidx)
     void *side[2];       // moving-wall side state, [2 walls][2 fields][hw][pitch]
     void *lag[2];        // lagged own-cell force sums sum_a A+^i_a s_a, [n1][2][pitch] (compute type)
     const void *tab;     // step table
@@ -75,12 +75,25 @@ struct InstDesc {
     const double *mB64;  // FP64 base mass per table entry
     long long plane;     // n1 * pitch: a population buffer holds Q * plane elements, a lag buffer 2 * plane
     long long sa, sr;    // element strides between directions and between rows of a population buffer
+    long long sb;        // element stride between column blocks of a row (see pidx)
+    int bs, bm;          // column block: j >> bs is the block, j & bm the position (bm = 2^bs - 1)
     long long lsa, lsr;  // the same for the two force-sum fields of a lag buffer
     int n1, n2, pitch, hw;
     int periodic1, bc_lo, bc_hi, cell;
     int iters, ncell, par0, pad;
     double ut_lo, ut_hi, a1, a2, omega, kpi;
 };
+
+// Element index of population a of cell (i, j) in a population buffer.  Each
+// row holds column blocks, each block its Q direction segments.  FP32 storage
+// uses blocks of 64 columns (bs = 6: a wave's pulls and stores touch a few
+// contiguous blocks); FP64 and FP16 storage, and rows narrower than 64, use
+// one block per row (bs = 30: [row][direction][column]).  Each choice was
+// the faster one measured for its storage type.
+__host__ __device__ inline size_t pidx(const InstDesc *d, int a, int i, int j)
+{
+    return (size_t)i * d->sr + (size_t)(j >> d->bs) * d->sb + (size_t)a * d->sa + (size_t)(j & d->bm);
+}
 
 // Source of the pulled population N_a(i, .) (Eq. adv, App. B): row r and
 // direction beta of the post-collision field, and the crossed wall (0 none,
@@ -258,9 +271,12 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
     }
 
     constexpr uint32_t ES = sizeof(S);
-    const uint32_t sa_b = (uint32_t)d->sa * ES, sr_b = (uint32_t)d->sr * ES;
+    const uint32_t sa_b = (uint32_t)d->sa * ES, sr_b = (uint32_t)d->sr * ES, sb_b = (uint32_t)d->sb * ES;
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(d->P[pin], (uint32_t)(plane * Q) * ES);
-    const uint32_t jb = (uint32_t)j * ES;
+    const int bs = d->bs, bm = d->bm;
+    const int lane = j - j0;
+    // byte offset of the wave's own cells inside a row
+    const uint32_t jb = (uint32_t)(j >> bs) * sb_b + (uint32_t)(j & bm) * ES;
 
     // ---- pull streaming with boundary sources ----
     T n[Q], s[Q];
@@ -268,22 +284,45 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
     const bool nowrap = (j0 >= CM) && (j0 + 63 + CM < n2);
     if (interior && nowrap) {
         // the whole stencil of the wave stays inside: source (i - c1, j - c2),
-        // same direction; the column shift rides in the scalar offset
+        // same direction
+        if constexpr (sizeof(S) == 4) {
+            // 64-column blocks (the fast path needs n2 > 64, so bs = 6):
+            // column j - c2 lies in block j0/64 - 1, j0/64 or j0/64 + 1
+            // (j0 >= 64 here); one per-lane offset per shift c2, counted from
+            // the start of block j0/64 - 1, which rides in the scalar offset
+            // with the direction and the source row
+            uint32_t vsh[2 * CM + 1];
 #pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            const uint32_t soff = (uint32_t)((int)(a * sa_b + (i - cx(a)) * sr_b) - cy(a) * (int)ES);
-            n[a] = pload<Q, S, T>(rin, jb, soff, a);
-            if (a > 0) n[a] += tb(TB::DB(a));
+            for (int k = -CM; k <= CM; ++k) {
+                const int p = 64 + lane - k;
+                vsh[k + CM] = (uint32_t)(p >> 6) * sb_b + (uint32_t)(p & 63) * ES;
+            }
+            const uint32_t blk = (uint32_t)((j0 >> 6) - 1) * sb_b;
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const uint32_t soff = (uint32_t)a * sa_b + (uint32_t)(i - cx(a)) * sr_b + blk;
+                n[a] = pload<Q, S, T>(rin, vsh[cy(a) + CM], soff, a);
+                if (a > 0) n[a] += tb(TB::DB(a));
+            }
+        } else {
+            // one block per row: the column shift rides in the scalar offset
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const uint32_t soff = (uint32_t)((int)(a * sa_b + (i - cx(a)) * sr_b) - cy(a) * (int)ES);
+                n[a] = pload<Q, S, T>(rin, jb, soff, a);
+                if (a > 0) n[a] += tb(TB::DB(a));
+            }
         }
     } else {
-        // byte offsets of the wrapped columns j - c2, c2 = -CM..CM (q2 is periodic)
+        // wrapped columns j - c2, c2 = -CM..CM (q2 is periodic), and their
+        // byte offsets inside a row
+        int colv[2 * CM + 1];
         uint32_t colb[2 * CM + 1];
-        if (n2 >= CM) {
 #pragma unroll
-            for (int k = -CM; k <= CM; ++k) colb[k + CM] = (uint32_t)wrap_col(j - k, n2) * ES;
-        } else {
-#pragma unroll
-            for (int k = -CM; k <= CM; ++k) colb[k + CM] = (uint32_t)(((j - k) % n2 + n2) % n2) * ES;
+        for (int k = -CM; k <= CM; ++k) {
+            const int c = n2 >= CM ? wrap_col(j - k, n2) : ((j - k) % n2 + n2) % n2;
+            colv[k + CM] = c;
+            colb[k + CM] = (uint32_t)(c >> bs) * sb_b + (uint32_t)(c & bm) * ES;
         }
         const T *side_in = (const T *)d->side[pin];
 #pragma unroll
@@ -299,7 +338,7 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
                 if ((sd ? bchi : bclo) == BC_MOVING) {
                     // App. B.3 moving-wall correction (tangential component)
                     const int k = sd ? (n1 - 1 - r) : r;
-                    const T *sp = side_in + ((size_t)(sd * 2) * hw + k) * pitch + cb / ES;
+                    const T *sp = side_in + ((size_t)(sd * 2) * hw + k) * pitch + colv[c2 + CM];
                     const T mz = sp[0];
                     const T uz = sp[(size_t)hw * pitch];
                     const T U0 = (T)(sd ? d->ut_hi : d->ut_lo);

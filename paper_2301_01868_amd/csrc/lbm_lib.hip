@@ -314,7 +314,7 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     const size_t nh = (size_t)H1 * H2;
     const int nf = geo_fields(q);
 
-    // FP64 persistent per-cell arrays
+    // FP64 per-cell arrays kept for the grid's lifetime
     g->X = (double *)dalloc(g, nh * 8);
     g->Y = (double *)dalloc(g, nh * 8);
     g->Jgeo = (double *)dalloc(g, (size_t)nc * 8);
@@ -436,11 +436,19 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     I.mom = g->mom;
     I.mB64 = g->mB64;
     I.plane = (long long)plane;
-    // populations [row][direction][column]: the Q row segments a wave's pulls
-    // and stores touch lie within 7 adjacent row blocks (measured faster than
-    // one plane per direction); the two force sums likewise [row][2][column]
-    I.sa = g->pitch;
-    I.sr = (long long)q * g->pitch;
+    // populations [row][column block][direction][block width] (pidx): FP32
+    // rows in blocks of 64 columns, FP64/FP16 rows (and rows narrower than
+    // 64) as one block, the faster layout measured for each storage type;
+    // the two force sums [row][2][column]
+    {
+        const bool blocks = g->precision == LBM_FP32 && g->pitch >= 64;
+        const int bw = blocks ? 64 : g->pitch;
+        I.bs = blocks ? 6 : 30;
+        I.bm = (1 << I.bs) - 1;
+        I.sa = bw;
+        I.sr = (long long)q * g->pitch;
+        I.sb = (long long)q * bw;
+    }
     I.lsa = g->pitch;
     I.lsr = 2LL * g->pitch;
     I.n1 = n1;

@@ -267,7 +267,7 @@ __global__ void k_init(const InstDesc *__restrict__ dd, InitArgs ia)
     S *P = (S *)d->P[ia.pin];
     for (int a = 0; a < Q; ++a) {
         const double N = m * feq_phi<Q>(a, U, U, G11, G12, G22);
-        P[(size_t)a * d->sa + (size_t)i * d->sr + j] = penc<Q, S, double>(N - ia.base[(size_t)e * Q + a], a);
+        P[pidx(d, a, i, j)] = penc<Q, S, double>(N - ia.base[(size_t)e * Q + a], a);
     }
     T *side = (T *)d->side[ia.pin];
     const int hw = d->hw;
@@ -295,10 +295,9 @@ __global__ void k_lag(const InstDesc *__restrict__ d, int pin)
     const T *tab = (const T *)d->tab;
     auto tv = [&](int f) { return d->cell ? tab[(size_t)f * d->ncell + c] : tab[(size_t)i * TB::STRIDE + f]; };
     const S *P = (const S *)d->P[pin];
-    const size_t off = (size_t)i * d->sr + j;
     T L1 = 0, L2 = 0;
     for (int a = 1; a < Q; ++a) {
-        const T v = pdec<Q, S, T>(P[(size_t)a * d->sa + off], a);
+        const T v = pdec<Q, S, T>(P[pidx(d, a, i, j)], a);
         L1 += tv(TB::A1(a)) * v;
         L2 += tv(TB::A2(a)) * v;
     }
@@ -322,7 +321,7 @@ __global__ void k_state_out(const InstDesc *__restrict__ d, const double *__rest
     const S *P = (const S *)d->P[pin];
     for (int a = 0; a < Q; ++a)
         out[(size_t)a * d->ncell + c] =
-            base[(size_t)e * Q + a] + pdec<Q, S, double>(P[(size_t)a * d->sa + (size_t)i * d->sr + j], a);
+            base[(size_t)e * Q + a] + pdec<Q, S, double>(P[pidx(d, a, i, j)], a);
 }
 
 template <int Q, typename S>
@@ -335,7 +334,7 @@ __global__ void k_state_in(const InstDesc *__restrict__ d, const double *__restr
     const int c = i * d->n2 + j, e = cellmode ? c : i;
     S *P = (S *)d->P[pin];
     for (int a = 0; a < Q; ++a)
-        P[(size_t)a * d->sa + (size_t)i * d->sr + j] =
+        P[pidx(d, a, i, j)] =
             penc<Q, S, double>(in[(size_t)a * d->ncell + c] - base[(size_t)e * Q + a], a);
 }
 
