@@ -122,6 +122,8 @@ typedef struct {
     int64_t step;
     double bytes_per_update;       /* algorithmic HBM bytes per lattice update: 2 Q sizeof(population) */
     size_t device_bytes;           /* device memory held by the grid */
+    int32_t waves_per_block;       /* step launch: waves (rows of 64 cells) per workgroup */
+    int32_t waves_per_cu_cap;      /* step launch: resident waves per CU cap, 0 = none */
 } lbm_grid_info;
 
 /* Lattice tables of App. A / App. B (host only): velocities cx[q], cy[q],
@@ -191,7 +193,8 @@ int lbm_geometry(lbm_grid *g, double *out);
 int lbm_synchronize(lbm_grid *g);
 void *lbm_stream(lbm_grid *g);
 
-/* Many grids advanced together: one launch per lattice and precision per step
+/* Many grids advanced together: one launch per group of grids sharing lattice,
+ * precision, table kind and force mode (lagged, or fixed-point passes) per step
  * over a flattened table of row tiles; steps of a batch are captured in HIP
  * graphs and run on the stream of grids[0] (grids on other streams are joined
  * with events before and after).  Every grid must be initialised
@@ -207,7 +210,7 @@ void lbm_batch_destroy(lbm_batch *b);
  * (after filling every record) if any grid has bad cells. */
 int lbm_batch_residuals(lbm_batch *b, lbm_resid *out);
 
-/* Group g of a batch (one lattice/precision/table kind, one kernel launch per
+/* Group g of a batch (one lattice/precision/table kind/force mode, one kernel launch per
  * step): returns the number of groups (>= 0) or an error; fills the lattice,
  * precision and total cells of group g when g is in range. */
 int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *precision, int64_t *cells);
@@ -222,12 +225,20 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n);
  * columns of one row; 0 = default 4). */
 int lbm_set_launch(lbm_grid *g, int32_t waves_per_block);
 
+/* Cap on the resident waves per CU of a grid's step launches (and of the
+ * batches made from it later): 0 = no cap, else 4..64 (LBM_EINVAL
+ * otherwise).  The cap is enforced by reserving unused LDS per workgroup; it
+ * trades memory-level parallelism against the number of DRAM pages open at
+ * once and changes no result. */
+int lbm_set_occupancy(lbm_grid *g, int32_t waves_per_cu);
+
 /* Autotuner: times `steps` step launches for each tile shape (1, 2 or 4
- * waves, i.e. rows, per workgroup), keeps the fastest and caches the choice
- * for the process per (q, precision, table kind, n1, n2).  The timing steps
- * run on the grid's own buffers, so call it between create and init (the
- * grid needs lbm_init afterwards).  Returns the chosen waves per workgroup
- * (> 0) or an error code. */
+ * waves, i.e. rows, per workgroup) and each occupancy cap (none, 24, 20 or
+ * 16 waves per CU), keeps the fastest pair and caches it for the process per
+ * (q, precision, table kind, n1, n2).  The timing steps run on the grid's own
+ * buffers, so call it between create and init (the grid needs lbm_init
+ * afterwards).  Returns the chosen waves per workgroup (> 0; the cap is in
+ * lbm_grid_info) or an error code. */
 int lbm_autotune(lbm_grid *g, int32_t steps);
 
 /* Plain device copy kernel (for calibrating memory-traffic counters): copies

@@ -237,7 +237,7 @@ struct TabView {
 // 64 columns per wave; MOM = true computes and writes the moments instead of
 // colliding.
 // ---------------------------------------------------------------------------
-template <int Q, typename T, typename S, bool CELL, bool MOM>
+template <int Q, typename T, typename S, bool CELL, bool MOM, bool ITER>
 __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts, const int4 *__restrict__ tiles,
                                               int par)
 {
@@ -375,7 +375,10 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
     const T ma1 = m * (T)d->a1, ma2 = m * (T)d->a2;
     const T G11 = tb(TB::G11), G12 = tb(TB::G12), G22 = tb(TB::G22);
     const T omega = (T)d->omega, omw = (T)1 - (T)d->omega;
-    const int iters = MOM ? 0 : d->iters;
+    // fixed-point passes of the force relation: only the ITER instances read
+    // the count; the others do the single lagged pass, so the pulled
+    // populations need not stay live past the collision
+    const int iters = (MOM || !ITER) ? 0 : d->iters;
 
     T JF1, JF2, Ut1, Ut2;
     // pulled part of the force sum: sum_a A+_a n_{-a} (pass independent)

@@ -48,6 +48,7 @@ struct lbm_grid {
     InstDesc *d_inst = nullptr;
     int4 *d_tiles = nullptr;
     int ntiles = 0, wpb = 4;
+    int cap = 0;                  // resident waves per CU (0: no cap), see occupancy_lds
     InstDesc h_inst{};
     int64_t step = 0;
     int par = 0;
@@ -66,10 +67,10 @@ struct lbm_batch {
     hipEvent_t ev = nullptr;
     double *d_res = nullptr;           // [grids][RED_NF] reduction results
     struct Group {
-        int q = 0, precision = 0, cell = 0;
+        int q = 0, precision = 0, cell = 0, iter = 0;
         InstDesc *d_inst = nullptr;
         int4 *d_tiles = nullptr;
-        int ntiles = 0, wpb = 4;
+        int ntiles = 0, wpb = 4, cap = 0;
     };
     std::vector<Group> groups;
     std::vector<void *> allocs;
@@ -127,27 +128,44 @@ static size_t comp_size(int precision) { return precision == LBM_FP64 ? sizeof(d
 
 static dim3 cell_grid(int n1, int n2) { return dim3((n2 + 127) / 128, n1); }
 
+// Dynamic LDS reserved per workgroup of a step launch to cap the resident
+// waves per CU at `cap` (0: no reservation).  The step kernels use no LDS;
+// the reservation only limits how many workgroups share a CU's 160 KiB.  At
+// most 64 KiB is reserved per workgroup, so caps below three workgroups per
+// CU are not enforced exactly.
+static unsigned occupancy_lds(int cap, int wpb)
+{
+    if (cap <= 0) return 0u;
+    const unsigned lds_per_cu = 160u * 1024u;
+    const unsigned wg = (unsigned)(cap / wpb > 1 ? cap / wpb : 1);
+    const unsigned b = (lds_per_cu / wg + 255u) & ~255u;
+    return b > 65536u ? 65536u : b;
+}
+
 // kernel dispatch tables -------------------------------------------------------
 typedef void (*StepFn)(const InstDesc *, const int4 *, int);
 
-template <int Q>
-static StepFn step_fn(int precision, int cell, int mom)
+template <int Q, bool CELL, bool MOM, bool ITER>
+static StepFn step_fn3(int precision)
 {
-    if (precision == LBM_FP64) {
-        if (cell) return mom ? k_step<Q, double, double, true, true> : k_step<Q, double, double, true, false>;
-        return mom ? k_step<Q, double, double, false, true> : k_step<Q, double, double, false, false>;
-    }
-    if (precision == LBM_FP16) {
-        if (cell) return mom ? k_step<Q, float, _Float16, true, true> : k_step<Q, float, _Float16, true, false>;
-        return mom ? k_step<Q, float, _Float16, false, true> : k_step<Q, float, _Float16, false, false>;
-    }
-    if (cell) return mom ? k_step<Q, float, float, true, true> : k_step<Q, float, float, true, false>;
-    return mom ? k_step<Q, float, float, false, true> : k_step<Q, float, float, false, false>;
+    if (precision == LBM_FP64) return k_step<Q, double, double, CELL, MOM, ITER>;
+    if (precision == LBM_FP16) return k_step<Q, float, _Float16, CELL, MOM, ITER>;
+    return k_step<Q, float, float, CELL, MOM, ITER>;
 }
 
-static StepFn pick_step(int q, int precision, int cell, int mom)
+template <int Q>
+static StepFn step_fn(int precision, int cell, int mom, int iter)
 {
-    return q == 9 ? step_fn<9>(precision, cell, mom) : step_fn<21>(precision, cell, mom);
+    if (mom) return cell ? step_fn3<Q, true, true, false>(precision) : step_fn3<Q, false, true, false>(precision);
+    if (iter) return cell ? step_fn3<Q, true, false, true>(precision) : step_fn3<Q, false, false, true>(precision);
+    return cell ? step_fn3<Q, true, false, false>(precision) : step_fn3<Q, false, false, false>(precision);
+}
+
+// kernel for a grid or batch group: lattice, storage precision, per-cell
+// tables, moments pass, fixed-point force passes (iterations > 0)
+static StepFn pick_step(int q, int precision, int cell, int mom, int iter)
+{
+    return q == 9 ? step_fn<9>(precision, cell, mom, iter) : step_fn<21>(precision, cell, mom, iter);
 }
 
 static std::vector<int4> make_tiles(int inst, int n1, int n2, int wpb)
@@ -212,8 +230,8 @@ static int build_tiles(lbm_grid *g)
 
 static int launch_step(lbm_grid *g, int par, int mom)
 {
-    StepFn fn = pick_step(g->q, g->precision, !g->row, mom);
-    hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), 0, g->stream, (const InstDesc *)g->d_inst,
+    StepFn fn = pick_step(g->q, g->precision, !g->row, mom, g->h_inst.iters > 0);
+    hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), occupancy_lds(g->cap, g->wpb), g->stream, (const InstDesc *)g->d_inst,
                        (const int4 *)g->d_tiles, par);
     HIPCHK(g, hipGetLastError());
     return LBM_OK;
@@ -489,6 +507,8 @@ int lbm_grid_info_get(const lbm_grid *g, lbm_grid_info *out)
     out->step = g->step;
     out->bytes_per_update = 2.0 * g->q * (double)store_size(g->precision);
     out->device_bytes = g->bytes;
+    out->waves_per_block = g->wpb;
+    out->waves_per_cu_cap = g->cap;
     return LBM_OK;
 }
 
@@ -501,9 +521,20 @@ int lbm_set_launch(lbm_grid *g, int32_t wpb)
     return build_tiles(g);
 }
 
+int lbm_set_occupancy(lbm_grid *g, int32_t waves_per_cu)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    if (waves_per_cu != 0 && (waves_per_cu < 4 || waves_per_cu > 64))
+        return fail(g, LBM_EINVAL, "waves per CU cap must be 0 or 4..64");
+    g->cap = waves_per_cu;
+    drop_graphs(g);
+    return LBM_OK;
+}
+
 namespace {
-// process-wide autotuner cache: (q, precision, cell tables, n1, n2) -> waves per block
-std::map<std::tuple<int, int, int, int, int>, int> g_tuned;
+// process-wide autotuner cache: (q, precision, cell tables, n1, n2) ->
+// (waves per block, waves per CU cap)
+std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tuned;
 } // namespace
 
 int lbm_autotune(lbm_grid *g, int32_t steps)
@@ -513,39 +544,45 @@ int lbm_autotune(lbm_grid *g, int32_t steps)
     const auto key = std::make_tuple(g->q, g->precision, g->row ? 0 : 1, g->n1, g->n2);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-        const int rc = lbm_set_launch(g, it->second);
-        return rc != LBM_OK ? rc : it->second;
+        int rc = lbm_set_launch(g, it->second.first);
+        if (rc == LBM_OK) rc = lbm_set_occupancy(g, it->second.second);
+        return rc != LBM_OK ? rc : it->second.first;
     }
     hipEvent_t e0, e1;
     HIPCHK(g, hipEventCreate(&e0));
     HIPCHK(g, hipEventCreate(&e1));
-    int best = 4;
+    int best_w = 4, best_c = 0;
     float best_ms = 1e30f;
     for (int w : {4, 2, 1}) {
-        int rc = lbm_set_launch(g, w);
-        for (int s = 0; rc == LBM_OK && s < 2; ++s) rc = launch_step(g, s & 1, 0);
-        HIPCHK(g, hipEventRecord(e0, g->stream));
-        for (int s = 0; rc == LBM_OK && s < steps; ++s) rc = launch_step(g, s & 1, 0);
-        HIPCHK(g, hipEventRecord(e1, g->stream));
-        HIPCHK(g, hipEventSynchronize(e1));
-        if (rc != LBM_OK) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return rc;
-        }
-        float ms = 0.f;
-        HIPCHK(g, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = w;
+        for (int c : {0, 24, 20, 16}) {
+            int rc = lbm_set_launch(g, w);
+            if (rc == LBM_OK) rc = lbm_set_occupancy(g, c);
+            for (int s = 0; rc == LBM_OK && s < 2; ++s) rc = launch_step(g, s & 1, 0);
+            HIPCHK(g, hipEventRecord(e0, g->stream));
+            for (int s = 0; rc == LBM_OK && s < steps; ++s) rc = launch_step(g, s & 1, 0);
+            HIPCHK(g, hipEventRecord(e1, g->stream));
+            HIPCHK(g, hipEventSynchronize(e1));
+            if (rc != LBM_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return rc;
+            }
+            float ms = 0.f;
+            HIPCHK(g, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_w = w;
+                best_c = c;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    g_tuned[key] = best;
+    g_tuned[key] = std::make_pair(best_w, best_c);
     g->inited = false;   // the timing steps ran on whatever state the grid held
-    const int rc = lbm_set_launch(g, best);
-    return rc != LBM_OK ? rc : best;
+    int rc = lbm_set_launch(g, best_w);
+    if (rc == LBM_OK) rc = lbm_set_occupancy(g, best_c);
+    return rc != LBM_OK ? rc : best_w;
 }
 
 int lbm_set_volume(lbm_grid *g, const double *J)
@@ -630,8 +667,8 @@ static int capture_graph(lbm_grid *g, int start_par, int steps)
     HIPCHK(g, hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
     int par = start_par;
     for (int s = 0; s < steps; ++s) {
-        StepFn fn = pick_step(g->q, g->precision, !g->row, 0);
-        hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), 0, g->stream, (const InstDesc *)g->d_inst,
+        StepFn fn = pick_step(g->q, g->precision, !g->row, 0, g->h_inst.iters > 0);
+        hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), occupancy_lds(g->cap, g->wpb), g->stream, (const InstDesc *)g->d_inst,
                            (const int4 *)g->d_tiles, par);
         par ^= 1;
     }
@@ -936,7 +973,7 @@ int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
     *out = nullptr;
     lbm_batch *b = new lbm_batch();
     b->stream = grids[0]->stream;
-    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
     for (int k = 0; k < n; ++k) {
         lbm_grid *g = grids[k];
         if (!g || !g->inited) {
@@ -950,14 +987,16 @@ int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
         if (g->stream != b->stream && std::find(b->others.begin(), b->others.end(), g->stream) == b->others.end())
             b->others.push_back(g->stream);
         b->grids.push_back(g);
-        groups[std::make_tuple(g->q, g->precision, g->row ? 0 : 1)].push_back(k);
+        groups[std::make_tuple(g->q, g->precision, g->row ? 0 : 1, g->h_inst.iters > 0 ? 1 : 0)].push_back(k);
     }
     for (auto &kv : groups) {
         lbm_batch::Group G;
         G.q = std::get<0>(kv.first);
         G.precision = std::get<1>(kv.first);
         G.cell = std::get<2>(kv.first);
+        G.iter = std::get<3>(kv.first);
         G.wpb = b->grids[kv.second[0]]->wpb;
+        G.cap = b->grids[kv.second[0]]->cap;
         std::vector<InstDesc> descs;
         std::vector<int4> nat;
         for (int k : kv.second) {
@@ -1021,8 +1060,8 @@ static int batch_join_out(lbm_batch *b)
 static int batch_launch(lbm_batch *b, int par)
 {
     for (auto &G : b->groups) {
-        StepFn fn = pick_step(G.q, G.precision, G.cell, 0);
-        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), 0, b->stream, (const InstDesc *)G.d_inst,
+        StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter);
+        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), occupancy_lds(G.cap, G.wpb), b->stream, (const InstDesc *)G.d_inst,
                            (const int4 *)G.d_tiles, par);
     }
     if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "batch step launch failed");
@@ -1105,7 +1144,9 @@ int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *preci
     if (cells) {
         int64_t c = 0;
         for (lbm_grid *g : b->grids)
-            if (g->q == G.q && g->precision == G.precision && (g->row ? 0 : 1) == G.cell) c += g->ncell;
+            if (g->q == G.q && g->precision == G.precision && (g->row ? 0 : 1) == G.cell &&
+                (g->h_inst.iters > 0 ? 1 : 0) == G.iter)
+                c += g->ncell;
         *cells = c;
     }
     return (int)b->groups.size();
@@ -1116,9 +1157,9 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n)
     if (!b || group < 0 || group >= (int32_t)b->groups.size() || n < 0 || (n & 1))
         return fail(nullptr, LBM_EINVAL, "bad group step arguments (n must be even)");
     const auto &G = b->groups[group];
-    StepFn fn = pick_step(G.q, G.precision, G.cell, 0);
+    StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter);
     for (int64_t k = 0; k < n; ++k)
-        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), 0, b->stream, (const InstDesc *)G.d_inst,
+        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), occupancy_lds(G.cap, G.wpb), b->stream, (const InstDesc *)G.d_inst,
                            (const int4 *)G.d_tiles, (int)((b->step + k) & 1));
     if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "group step launch failed");
     return LBM_OK;

@@ -24,7 +24,7 @@ BC = {"periodic": LBM_PERIODIC, "noslip": LBM_NOSLIP, "moving": LBM_MOVING}
 EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_error", "lbm_grid_info_get",
             "lbm_set_volume", "lbm_get_volume", "lbm_init", "lbm_step", "lbm_moments", "lbm_residual", "lbm_noflow_adjust",
             "lbm_get_state", "lbm_set_state", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
-            "lbm_stream", "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_autotune",
+            "lbm_stream", "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_set_occupancy", "lbm_autotune",
             "lbm_copy_probe", "lbm_bandwidth_probe"]
 
 
@@ -59,7 +59,8 @@ class lbm_resid(ct.Structure):
 class lbm_grid_info(ct.Structure):
     _fields_ = [("q", ct.c_int32), ("n1", ct.c_int32), ("n2", ct.c_int32), ("pitch", ct.c_int32),
                 ("precision", ct.c_int32), ("row_tables", ct.c_int32), ("step", ct.c_int64),
-                ("bytes_per_update", ct.c_double), ("device_bytes", ct.c_size_t)]
+                ("bytes_per_update", ct.c_double), ("device_bytes", ct.c_size_t),
+                ("waves_per_block", ct.c_int32), ("waves_per_cu_cap", ct.c_int32)]
 
 
 _lib = None
@@ -105,6 +106,7 @@ def load():
     L.lbm_batch_info.argtypes = [vp, ct.c_int32, I32, I32, ct.POINTER(ct.c_int64)]
     L.lbm_batch_step_group.argtypes = [vp, ct.c_int32, ct.c_int64]
     L.lbm_set_launch.argtypes = [vp, ct.c_int32]
+    L.lbm_set_occupancy.argtypes = [vp, ct.c_int32]
     L.lbm_autotune.argtypes = [vp, ct.c_int32]
     L.lbm_copy_probe.argtypes = [vp, vp, ct.c_size_t, vp]
     L.lbm_bandwidth_probe.argtypes = [vp, vp, ct.c_size_t, ct.c_int32, vp]
@@ -256,6 +258,10 @@ def lbm_set_launch(h, waves_per_block):
     _chk(load().lbm_set_launch(h, int(waves_per_block)), h)
 
 
+def lbm_set_occupancy(h, waves_per_cu):
+    _chk(load().lbm_set_occupancy(h, int(waves_per_cu)), h)
+
+
 def lbm_batch_create(handles):
     arr = (ct.c_void_p * len(handles))(*[h.value if isinstance(h, ct.c_void_p) else h for h in handles])
     b = ct.c_void_p()
@@ -375,6 +381,9 @@ class Grid:
 
     def set_launch(self, wpb):
         lbm_set_launch(self.h, wpb)
+
+    def set_occupancy(self, waves_per_cu):
+        lbm_set_occupancy(self.h, waves_per_cu)
 
     def autotune(self, steps=20):
         return lbm_autotune(self.h, steps)

@@ -47,19 +47,22 @@ def test_batch_equals_alone(prec):
 
 
 def test_launch_shape_does_not_change_results():
-    """Tile shape (waves per workgroup) and the autotuner's choice leave every
-    cell's arithmetic unchanged: bitwise identical states."""
+    """Tile shape (waves per workgroup), the occupancy cap and the autotuner's
+    choice leave every cell's arithmetic unchanged: bitwise identical states."""
     case = G.circular_couette(21, 13, 140, 12.0, u_inner=0.05, tau=0.7)
     states = []
-    for w in (1, 2, 4):
+    for w, cap in ((1, 0), (2, 0), (4, 0), (1, 20), (2, 16), (4, 24)):
         g = lbm.Grid(case, precision=lbm.LBM_FP32)
         g.set_launch(w)
+        g.set_occupancy(cap)
+        assert (g.info.waves_per_block, g.info.waves_per_cu_cap) == (w, cap)
         g.init()
         g.step(77)
         states.append(g.get_state()[0])
     g = lbm.Grid(case, precision=lbm.LBM_FP32)
     chosen = g.autotune(6)
     assert chosen in (1, 2, 4)
+    assert g.info.waves_per_block == chosen and g.info.waves_per_cu_cap in (0, 24, 20, 16)
     g.init()
     g.step(77)
     states.append(g.get_state()[0])
@@ -105,3 +108,27 @@ def test_batch_rejects_repeated_or_uninitialised_grids():
     Pa, _ = a.get_state()
     Pb, _ = b.get_state()
     assert np.array_equal(Pa, Pb)
+
+
+def test_batch_with_fixed_point_force_grids():
+    """Grids with fixed-point force passes (iterations > 0) form their own
+    launch group; each grid still ends exactly as it does alone."""
+    cases = [(G.planar_couette(9, G.faces_linear(12, 0.4), n2=70, u_wall=0.05, tau=0.8), 2),
+             (G.planar_couette(9, G.faces_linear(12, 0.4), n2=70, u_wall=0.05, tau=0.8), 0),
+             (G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, tau=0.8), 1)]
+    alone = [lbm.Grid(c, precision=lbm.LBM_FP64, iterations=k) for c, k in cases]
+    mixed = [lbm.Grid(c, precision=lbm.LBM_FP64, iterations=k) for c, k in cases]
+    for g in alone + mixed:
+        g.init()
+    for g in alone:
+        g.step(40)
+    b = lbm.lbm_batch_create([g.h for g in mixed])
+    groups = lbm.lbm_batch_groups(b)
+    say("groups", groups)
+    assert len(groups) == 3
+    lbm.lbm_batch_step(b, 40)
+    lbm.lbm_batch_destroy(b)
+    for ga, gm in zip(alone, mixed):
+        assert np.array_equal(ga.get_state()[0], gm.get_state()[0])
+    # the fixed-point passes change the result
+    assert not np.array_equal(mixed[0].get_state()[0], mixed[1].get_state()[0])
