@@ -5,7 +5,8 @@ residual tolerance.  They arrive over time; the server keeps every admitted
 solve's populations resident in HBM, admits new solves between rounds as
 device memory frees up (an HBM budget), advances all resident solves together
 with one batched launch per lattice group per step (HIP-graph captured), checks
-each solve's residual every round, and retires converged (or unstable) solves.
+each solve's residual every round, and retires solves that converged, turned
+unstable, stalled (residual no longer falling) or reached the step limit.
 The sequential baseline replays the same trace one solve at a time, first come
 first served, in FP64.
 
@@ -36,6 +37,29 @@ class Request:
     residual: float = math.nan
     status: str = "pending"
     result: dict = field(default_factory=dict)
+    best: float = math.inf        # lowest residual that halved the previous best
+    best_step: int = 0            # step count at which `best` was reached
+
+
+def check_progress(r, res, max_steps, stall_steps):
+    """Record a residual check of request `r` after its steps were counted;
+    return its final status, or None while it keeps running.  A solve whose
+    residual has not halved within `stall_steps` steps is stalled: a
+    converging solve halves it every ln 2 times its slowest decay time, while
+    a solve caught in a saturated unsteady state (an instability of the
+    scheme that does not overflow) keeps it level."""
+    r.residual = res.residual
+    if res.bad_cells > 0:
+        return "unstable"
+    if res.residual < r.tol:
+        return "converged"
+    if res.residual < 0.5 * r.best:
+        r.best, r.best_step = res.residual, r.steps
+    if r.steps - r.best_step >= stall_steps:
+        return "stalled"
+    if r.steps >= max_steps:
+        return "max_steps"
+    return None
 
 
 def request_bytes(case, precision):
@@ -80,11 +104,12 @@ def make_trace(seed=2301_01869, rate=50.0, duration=60.0, n_min=16, n_max=128, t
 
 class Server:
     def __init__(self, hbm_budget=8 << 30, check_every=200, precision=lbm.LBM_FP32, max_steps=2_000_000,
-                 stream=None):
+                 stream=None, stall_steps=200_000):
         self.budget = hbm_budget
         self.K = check_every
         self.precision = precision
         self.max_steps = max_steps
+        self.stall_steps = stall_steps
         self.stream = stream
 
     def run(self, requests, realtime=True):
@@ -130,15 +155,9 @@ class Server:
             recs = lbm.lbm_batch_residuals(batch, len(items))
             for (rid, (r, g, need)), res in zip(items, recs):
                 r.steps += self.K
-                r.residual = res.residual
-                if res.bad_cells > 0:
-                    r.status = "unstable"
-                    done.append(rid)
-                elif res.residual < r.tol:
-                    r.status = "converged"
-                    done.append(rid)
-                elif r.steps >= self.max_steps:
-                    r.status = "max_steps"
+                st = check_progress(r, res, self.max_steps, self.stall_steps)
+                if st is not None:
+                    r.status = st
                     done.append(rid)
             if done:
                 now = time.perf_counter() - t0
@@ -156,7 +175,7 @@ class Server:
 
 
 def run_sequential(requests, precision=lbm.LBM_FP64, check_every=200, max_steps=2_000_000, stream=None,
-                   realtime=True):
+                   realtime=True, stall_steps=200_000):
     """Plain one-solve-at-a-time stepping, first come first served."""
     t0 = time.perf_counter()
     for r in sorted(requests, key=lambda r: r.arrival):
@@ -169,16 +188,9 @@ def run_sequential(requests, precision=lbm.LBM_FP64, check_every=200, max_steps=
         while True:
             g.step(check_every)
             r.steps += check_every
-            res = g.residual(check=False)
-            r.residual = res.residual
-            if res.bad_cells > 0:
-                r.status = "unstable"
-                break
-            if res.residual < r.tol:
-                r.status = "converged"
-                break
-            if r.steps >= max_steps:
-                r.status = "max_steps"
+            st = check_progress(r, g.residual(check=False), max_steps, stall_steps)
+            if st is not None:
+                r.status = st
                 break
         m, U, Ut = g.moments()
         r.result = {"Ut": Ut}
@@ -193,6 +205,8 @@ def summarize(requests, makespan):
     lups = sum(r.steps * r.case.ncell for r in requests)
     return {"requests": len(requests), "converged": len(ok),
             "unstable": sum(r.status == "unstable" for r in requests),
+            "stalled": sum(r.status == "stalled" for r in requests),
+            "max_steps": sum(r.status == "max_steps" for r in requests),
             "solves_per_s": len(ok) / makespan if makespan > 0 else 0.0,
             "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
