@@ -202,6 +202,16 @@ void *lbm_stream(lbm_grid *g);
  * The batch does not own the grids: destroy the batch before its grids.
  * While it is in a batch a grid must only be stepped through the batch. */
 int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out);
+
+/* lbm_batch_create with options.  LBM_BATCH_FUSE_LATTICES puts D2Q9 and D2Q21
+ * grids of one precision, table kind and force mode into a single launch per
+ * step (each workgroup runs its tile's lattice): half the kernel launches of a
+ * mixed batch, which shortens the steps of small, launch-bound batches (the
+ * serving loop), at some cost in throughput on large ones, since both
+ * lattices then run with the larger kernel's register allocation.  Other
+ * flag bits: LBM_EINVAL. */
+enum { LBM_BATCH_FUSE_LATTICES = 1 };
+int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_batch **out);
 int lbm_batch_step(lbm_batch *b, int64_t n);
 void lbm_batch_destroy(lbm_batch *b);
 
@@ -211,8 +221,9 @@ void lbm_batch_destroy(lbm_batch *b);
 int lbm_batch_residuals(lbm_batch *b, lbm_resid *out);
 
 /* Group g of a batch (one lattice/precision/table kind/force mode, one kernel launch per
- * step): returns the number of groups (>= 0) or an error; fills the lattice,
- * precision and total cells of group g when g is in range. */
+ * step): returns the number of groups (>= 0) or an error; fills the lattice
+ * (0 for a fused group holding both lattices), precision and total cells of
+ * group g when g is in range. */
 int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *precision, int64_t *cells);
 
 /* Measurement hook: launch only group g's step kernel n times (n even, so

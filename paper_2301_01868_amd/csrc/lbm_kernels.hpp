@@ -238,15 +238,13 @@ struct TabView {
 // colliding.
 // ---------------------------------------------------------------------------
 template <int Q, typename T, typename S, bool CELL, bool MOM, bool ITER>
-__global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts, const int4 *__restrict__ tiles,
-                                              int par)
+__device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, const int4 tl, int par)
 {
     constexpr int CM = cmax<Q>();
     constexpr int NP = npair<Q>();
     constexpr double T0d = lattice_T0<Q>();
     using TB = Tab<Q>;
 
-    const int4 tl = tiles[blockIdx.x];
     const InstDesc *__restrict__ d = insts + tl.x;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int i = tl.y + wave;
@@ -527,6 +525,28 @@ __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts
             side_out[((size_t)3 * hw + k) * pitch + j] = Ut2;
         }
     }
+}
+
+// One tile (row segment of 64 columns per wave) per workgroup.  The tile
+// table holds (instance, first row, first column, lattice).
+template <int Q, typename T, typename S, bool CELL, bool MOM, bool ITER>
+__global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts, const int4 *__restrict__ tiles,
+                                              int par)
+{
+    step_tile<Q, T, S, CELL, MOM, ITER>(insts, tiles[blockIdx.x], par);
+}
+
+// D2Q9 and D2Q21 tiles in one launch: the lattice is the tile's fourth field
+// (wave-uniform, so each workgroup runs one of the two bodies).
+template <typename T, typename S, bool CELL, bool MOM, bool ITER>
+__global__ __launch_bounds__(256) void k_step_mixed(const InstDesc *__restrict__ insts,
+                                                    const int4 *__restrict__ tiles, int par)
+{
+    const int4 tl = tiles[blockIdx.x];
+    if (tl.w == 9)
+        step_tile<9, T, S, CELL, MOM, ITER>(insts, tl, par);
+    else
+        step_tile<21, T, S, CELL, MOM, ITER>(insts, tl, par);
 }
 
 } // namespace lbm

@@ -163,17 +163,31 @@ static StepFn step_fn(int precision, int cell, int mom, int iter)
 
 // kernel for a grid or batch group: lattice, storage precision, per-cell
 // tables, moments pass, fixed-point force passes (iterations > 0)
+template <bool CELL, bool ITER>
+static StepFn mixed_fn(int precision)
+{
+    if (precision == LBM_FP64) return k_step_mixed<double, double, CELL, false, ITER>;
+    if (precision == LBM_FP16) return k_step_mixed<float, _Float16, CELL, false, ITER>;
+    return k_step_mixed<float, float, CELL, false, ITER>;
+}
+
+// q = 0: a batch group holding both lattices (one fused launch, no moments pass)
 static StepFn pick_step(int q, int precision, int cell, int mom, int iter)
 {
+    if (q == 0) {
+        if (iter) return cell ? mixed_fn<true, true>(precision) : mixed_fn<false, true>(precision);
+        return cell ? mixed_fn<true, false>(precision) : mixed_fn<false, false>(precision);
+    }
     return q == 9 ? step_fn<9>(precision, cell, mom, iter) : step_fn<21>(precision, cell, mom, iter);
 }
 
-static std::vector<int4> make_tiles(int inst, int n1, int n2, int wpb)
+// tiles of one grid in row-major order: (instance, first row, first column, lattice)
+static std::vector<int4> make_tiles(int inst, int n1, int n2, int wpb, int q)
 {
     std::vector<int4> nat;
     const int ncs = (n2 + 63) / 64;
     for (int r0 = 0; r0 < n1; r0 += wpb)
-        for (int cs = 0; cs < ncs; ++cs) nat.push_back(make_int4(inst, r0, cs * 64, 0));
+        for (int cs = 0; cs < ncs; ++cs) nat.push_back(make_int4(inst, r0, cs * 64, q));
     return nat;
 }
 
@@ -216,7 +230,7 @@ static void drop_graphs(lbm_grid *g)
 
 static int build_tiles(lbm_grid *g)
 {
-    auto nat = make_tiles(0, g->n1, g->n2, g->wpb);
+    auto nat = make_tiles(0, g->n1, g->n2, g->wpb, g->q);
     auto ord = xcd_order(nat, g->n1);
     if (g->d_tiles) dfree(g, g->d_tiles);
     g->d_tiles = (int4 *)dalloc(g, ord.size() * sizeof(int4));
@@ -969,7 +983,14 @@ void lbm_batch_destroy(lbm_batch *b)
 
 int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
 {
-    if (!grids || n <= 0 || !out) return fail(nullptr, LBM_EINVAL, "bad batch arguments");
+    return lbm_batch_create_ex(grids, n, 0u, out);
+}
+
+int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_batch **out)
+{
+    if (!grids || n <= 0 || !out || (flags & ~(uint32_t)LBM_BATCH_FUSE_LATTICES))
+        return fail(nullptr, LBM_EINVAL, "bad batch arguments");
+    const bool fuse = (flags & LBM_BATCH_FUSE_LATTICES) != 0;
     *out = nullptr;
     lbm_batch *b = new lbm_batch();
     b->stream = grids[0]->stream;
@@ -987,11 +1008,14 @@ int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
         if (g->stream != b->stream && std::find(b->others.begin(), b->others.end(), g->stream) == b->others.end())
             b->others.push_back(g->stream);
         b->grids.push_back(g);
-        groups[std::make_tuple(g->q, g->precision, g->row ? 0 : 1, g->h_inst.iters > 0 ? 1 : 0)].push_back(k);
+        groups[std::make_tuple(fuse ? 0 : g->q, g->precision, g->row ? 0 : 1, g->h_inst.iters > 0 ? 1 : 0)].push_back(k);
     }
     for (auto &kv : groups) {
         lbm_batch::Group G;
-        G.q = std::get<0>(kv.first);
+        // a fused group with a single lattice keeps that lattice's kernel
+        G.q = b->grids[kv.second[0]]->q;
+        for (int k : kv.second)
+            if (b->grids[k]->q != G.q) G.q = 0;
         G.precision = std::get<1>(kv.first);
         G.cell = std::get<2>(kv.first);
         G.iter = std::get<3>(kv.first);
@@ -1005,7 +1029,7 @@ int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
             I.par0 = g->par;
             const int inst = (int)descs.size();
             descs.push_back(I);
-            auto t = make_tiles(inst, g->n1, g->n2, G.wpb);
+            auto t = make_tiles(inst, g->n1, g->n2, G.wpb, g->q);
             nat.insert(nat.end(), t.begin(), t.end());
         }
         // largest instances' tiles first would help tail balance; keep the
@@ -1144,7 +1168,7 @@ int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *preci
     if (cells) {
         int64_t c = 0;
         for (lbm_grid *g : b->grids)
-            if (g->q == G.q && g->precision == G.precision && (g->row ? 0 : 1) == G.cell &&
+            if ((G.q == 0 || g->q == G.q) && g->precision == G.precision && (g->row ? 0 : 1) == G.cell &&
                 (g->h_inst.iters > 0 ? 1 : 0) == G.iter)
                 c += g->ncell;
         *cells = c;

@@ -19,12 +19,13 @@ LBM_PERIODIC, LBM_NOSLIP, LBM_MOVING = 0, 1, 2
 LBM_FP64, LBM_FP32, LBM_FP16 = 0, 1, 2
 LBM_BASE_LOCAL_REST, LBM_BASE_W_RHO0, LBM_BASE_NONE = 0, 1, 2
 LBM_GEOM_AUTO, LBM_GEOM_CELL = 0, 1
+LBM_BATCH_FUSE_LATTICES = 1
 BC = {"periodic": LBM_PERIODIC, "noslip": LBM_NOSLIP, "moving": LBM_MOVING}
 
 EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_error", "lbm_grid_info_get",
             "lbm_set_volume", "lbm_get_volume", "lbm_init", "lbm_step", "lbm_moments", "lbm_residual", "lbm_noflow_adjust",
             "lbm_get_state", "lbm_set_state", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
-            "lbm_stream", "lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_set_occupancy", "lbm_autotune",
+            "lbm_stream", "lbm_batch_create", "lbm_batch_create_ex", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_set_occupancy", "lbm_autotune",
             "lbm_copy_probe", "lbm_bandwidth_probe"]
 
 
@@ -99,6 +100,7 @@ def load():
     L.lbm_stream.argtypes = [vp]
     L.lbm_stream.restype = vp
     L.lbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int32, ct.POINTER(vp)]
+    L.lbm_batch_create_ex.argtypes = [ct.POINTER(vp), ct.c_int32, ct.c_uint32, ct.POINTER(vp)]
     L.lbm_batch_step.argtypes = [vp, ct.c_int64]
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_destroy.restype = None
@@ -266,6 +268,13 @@ def lbm_batch_create(handles):
     arr = (ct.c_void_p * len(handles))(*[h.value if isinstance(h, ct.c_void_p) else h for h in handles])
     b = ct.c_void_p()
     _chk(load().lbm_batch_create(arr, len(handles), ct.byref(b)))
+    return b
+
+
+def lbm_batch_create_ex(handles, flags=0):
+    arr = (ct.c_void_p * len(handles))(*[h.value if isinstance(h, ct.c_void_p) else h for h in handles])
+    b = ct.c_void_p()
+    _chk(load().lbm_batch_create_ex(arr, len(handles), ct.c_uint32(flags), ct.byref(b)))
     return b
 
 

@@ -4,7 +4,7 @@ Requests are steady-state solves: a grid, a lattice, a relaxation time and a
 residual tolerance.  They arrive over time; the server keeps every admitted
 solve's populations resident in HBM, admits new solves between rounds as
 device memory frees up (an HBM budget), advances all resident solves together
-with one batched launch per lattice group per step (HIP-graph captured), checks
+with one fused batched launch per step (HIP-graph captured), checks
 each solve's residual every round, and retires solves that converged, turned
 unstable, stalled (residual no longer falling) or reached the step limit.
 The sequential baseline replays the same trace one solve at a time, first come
@@ -146,7 +146,9 @@ class Server:
             if dirty:
                 if batch is not None:
                     lbm.lbm_batch_destroy(batch)
-                batch = lbm.lbm_batch_create([g.h for (_, g, _) in active.values()])
+                # one fused launch per step for both lattices: the resident solves
+                # are small and their steps launch-bound
+                batch = lbm.lbm_batch_create_ex([g.h for (_, g, _) in active.values()], lbm.LBM_BATCH_FUSE_LATTICES)
                 dirty = False
             lbm.lbm_batch_step(batch, self.K)
             rounds += 1

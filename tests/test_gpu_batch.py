@@ -46,6 +46,28 @@ def test_batch_equals_alone(prec):
         assert np.array_equal(sa, sm)
 
 
+@pytest.mark.parametrize("prec", [lbm.LBM_FP64, lbm.LBM_FP32, lbm.LBM_FP16], ids=["fp64", "fp32", "fp16"])
+def test_fused_lattice_batch_equals_alone(prec):
+    """D2Q9 and D2Q21 grids in one fused launch per step end exactly as alone."""
+    cases = _cases()
+    alone = [lbm.Grid(c, precision=prec) for c in cases]
+    fused = [lbm.Grid(c, precision=prec) for c in cases]
+    for g in alone + fused:
+        g.init()
+    steps = 37
+    for g in alone:
+        g.step(steps)
+    b = lbm.lbm_batch_create_ex([g.h for g in fused], lbm.LBM_BATCH_FUSE_LATTICES)
+    groups = lbm.lbm_batch_groups(b)
+    say("fused groups", groups)
+    assert len(groups) == 1 and groups[0][0] == 0 and groups[0][2] == sum(c.ncell for c in cases)
+    lbm.lbm_batch_step(b, steps)
+    lbm.lbm_batch_destroy(b)
+    for ga, gf, c in zip(alone, fused, cases):
+        assert np.array_equal(ga.get_state()[0], gf.get_state()[0]), c.meta
+        assert np.array_equal(ga.get_state()[1], gf.get_state()[1])
+
+
 def test_launch_shape_does_not_change_results():
     """Tile shape (waves per workgroup), the occupancy cap and the autotuner's
     choice leave every cell's arithmetic unchanged: bitwise identical states."""
