@@ -110,16 +110,18 @@ def cpu_baseline(case, target_s=15.0, single_s=6.0):
             "single_core_value": case.ncell * k1 / dt1 / 1e6, "cpu_model": cpu_model()}
 
 
-def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbatched=False):
+def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbatched=False, iterations=0):
     """Create, initialise and time `steps` steps of the workload; returns a dict.
     With unbatched=True a batched workload is also timed one grid at a time
-    (each grid stepped alone through its own graphs, one after the other)."""
+    (each grid stepped alone through its own graphs, one after the other).
+    iterations > 0 runs the fixed-point passes of the force relation instead
+    of the lagged force."""
     import torch
     from paper_2301_01868_amd import lbm
 
     grids = []
     for c in cases:
-        g = lbm.Grid(c, precision=prec, stream=ct_stream(stream))
+        g = lbm.Grid(c, precision=prec, stream=ct_stream(stream), iterations=iterations)
         if wpb:
             g.set_launch(wpb)
         else:
@@ -171,7 +173,7 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
         kname = "k_step<%d,%s,row> (batch group of %d cells)" % (q, sname, kcells)
     alg_bytes = 2 * q * s_bytes * kcells
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = recorded_traffic(workload, sname, kcells) if workload else None
+    traffic = recorded_traffic(workload, sname, kcells) if (workload and iterations == 0) else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
             "bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_ms * 1e3, 3)}
@@ -212,6 +214,8 @@ def main():
                     help="serving benchmark: continuous batching vs sequential FP64 on a Poisson trace")
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--duration", type=float, default=20.0)
+    ap.add_argument("--iterations", type=int, default=0,
+                    help="fixed-point passes of the force relation (0: the paper's lagged force)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the library's plain copy kernel on MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -271,14 +275,16 @@ def main():
         return
     cases = workloads()[args.workload]()
     stream = torch.cuda.Stream()
-    r32 = measure(cases, lbm.LBM_FP32, args.steps, args.warmup, args.wpb, stream, args.workload, unbatched=True)
+    it = args.iterations
+    r32 = measure(cases, lbm.LBM_FP32, args.steps, args.warmup, args.wpb, stream, args.workload, unbatched=True,
+                  iterations=it)
     r64 = None
     if not args.no_fp64:
         r64 = measure(cases, lbm.LBM_FP64, max(2, args.steps // 2), max(2, args.warmup // 2), args.wpb, stream,
-                      args.workload)
+                      args.workload, iterations=it)
     r16 = None
     if not args.no_fp16:
-        r16 = measure(cases, lbm.LBM_FP16, args.steps, args.warmup, args.wpb, stream, args.workload)
+        r16 = measure(cases, lbm.LBM_FP16, args.steps, args.warmup, args.wpb, stream, args.workload, iterations=it)
 
     cpu = None
     if not args.no_cpu:
@@ -300,6 +306,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": r32["cells"], "q21_cells": r32["q21_cells"],
                    "grids": len(cases), "precision": "fp32 populations (offsets from the local rest state)",
+                   "force": "lagged" if it == 0 else "%d fixed-point passes" % it,
                    "bad_cells_after": r32["bad_cells"], "unstable_instances": r32["unstable"]},
         "roofline": r32["roofline"],
         "cpu_baseline": cpu,
