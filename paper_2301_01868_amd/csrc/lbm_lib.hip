@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -548,7 +549,9 @@ int lbm_set_occupancy(lbm_grid *g, int32_t waves_per_cu)
 namespace {
 // process-wide autotuner cache: (q, precision, cell tables, n1, n2) ->
 // (waves per block, waves per CU cap)
+// (shared by every grid of the process, so guarded)
 std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tuned;
+std::mutex g_tuned_mu;
 } // namespace
 
 int lbm_autotune(lbm_grid *g, int32_t steps)
@@ -556,15 +559,29 @@ int lbm_autotune(lbm_grid *g, int32_t steps)
     if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
     if (steps < 2) steps = 2;
     const auto key = std::make_tuple(g->q, g->precision, g->row ? 0 : 1, g->n1, g->n2);
-    auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) {
-        int rc = lbm_set_launch(g, it->second.first);
-        if (rc == LBM_OK) rc = lbm_set_occupancy(g, it->second.second);
-        return rc != LBM_OK ? rc : it->second.first;
+    {
+        std::pair<int, int> hit{0, 0};
+        {
+            std::lock_guard<std::mutex> lk(g_tuned_mu);
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) hit = it->second;
+        }
+        if (hit.first) {
+            int rc = lbm_set_launch(g, hit.first);
+            if (rc == LBM_OK) rc = lbm_set_occupancy(g, hit.second);
+            return rc != LBM_OK ? rc : hit.first;
+        }
     }
-    hipEvent_t e0, e1;
-    HIPCHK(g, hipEventCreate(&e0));
-    HIPCHK(g, hipEventCreate(&e1));
+    struct Events {   // destroyed on every return path
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events()
+        {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    HIPCHK(g, hipEventCreate(&ev.e0));
+    HIPCHK(g, hipEventCreate(&ev.e1));
     int best_w = 4, best_c = 0;
     float best_ms = 1e30f;
     for (int w : {4, 2, 1}) {
@@ -572,17 +589,14 @@ int lbm_autotune(lbm_grid *g, int32_t steps)
             int rc = lbm_set_launch(g, w);
             if (rc == LBM_OK) rc = lbm_set_occupancy(g, c);
             for (int s = 0; rc == LBM_OK && s < 2; ++s) rc = launch_step(g, s & 1, 0);
-            HIPCHK(g, hipEventRecord(e0, g->stream));
+            if (rc != LBM_OK) return rc;
+            HIPCHK(g, hipEventRecord(ev.e0, g->stream));
             for (int s = 0; rc == LBM_OK && s < steps; ++s) rc = launch_step(g, s & 1, 0);
-            HIPCHK(g, hipEventRecord(e1, g->stream));
-            HIPCHK(g, hipEventSynchronize(e1));
-            if (rc != LBM_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return rc;
-            }
+            if (rc != LBM_OK) return rc;
+            HIPCHK(g, hipEventRecord(ev.e1, g->stream));
+            HIPCHK(g, hipEventSynchronize(ev.e1));
             float ms = 0.f;
-            HIPCHK(g, hipEventElapsedTime(&ms, e0, e1));
+            HIPCHK(g, hipEventElapsedTime(&ms, ev.e0, ev.e1));
             if (ms < best_ms) {
                 best_ms = ms;
                 best_w = w;
@@ -590,9 +604,10 @@ int lbm_autotune(lbm_grid *g, int32_t steps)
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    g_tuned[key] = std::make_pair(best_w, best_c);
+    {
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        g_tuned[key] = std::make_pair(best_w, best_c);
+    }
     g->inited = false;   // the timing steps ran on whatever state the grid held
     int rc = lbm_set_launch(g, best_w);
     if (rc == LBM_OK) rc = lbm_set_occupancy(g, best_c);
