@@ -61,7 +61,10 @@ struct Tab {
     __host__ __device__ static constexpr int X11(int p) { return PB(p) + 3; }
     __host__ __device__ static constexpr int X12(int p) { return PB(p) + 4; }
     __host__ __device__ static constexpr int X22(int p) { return PB(p) + 5; }
-    static constexpr int W = 8 + 3 * (Q - 1) + 6 * NP;
+    // per direction a = 0..Q-1: compute base minus storage base (added to a
+    // computed offset to store it)
+    __host__ __device__ static constexpr int SB(int a) { return 8 + 3 * (Q - 1) + 6 * NP + a; }
+    static constexpr int W = 8 + 3 * (Q - 1) + 6 * NP + Q;
     static constexpr int STRIDE = (W + 3) & ~3;   // row stride, 16-byte multiple for FP32
 };
 
@@ -300,7 +303,8 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             for (int a = 0; a < Q; ++a) {
                 const uint32_t soff = (uint32_t)a * sa_b + (uint32_t)(i - cx(a)) * sr_b + blk;
                 n[a] = pload<Q, S, T>(rin, vsh[cy(a) + CM], soff, a);
-                if (a > 0) n[a] += tb(TB::DB(a));
+                // to this cell's compute base (the rest direction pulls from the cell itself)
+                n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             }
         } else {
             // one block per row: the column shift rides in the scalar offset
@@ -308,7 +312,8 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             for (int a = 0; a < Q; ++a) {
                 const uint32_t soff = (uint32_t)((int)(a * sa_b + (i - cx(a)) * sr_b) - cy(a) * (int)ES);
                 n[a] = pload<Q, S, T>(rin, jb, soff, a);
-                if (a > 0) n[a] += tb(TB::DB(a));
+                // to this cell's compute base (the rest direction pulls from the cell itself)
+                n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             }
         }
     } else {
@@ -330,7 +335,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             pull_source(i, a, n1, per1, bclo, bchi, r, beta, wall);
             const uint32_t cb = colb[c2 + CM];
             T v = pload<Q, S, T>(rin, cb, (uint32_t)beta * sa_b + (uint32_t)r * sr_b, a);
-            if (a > 0) v += tb(TB::DB(a));
+            v += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             if (c2 != 0 && wall != 0) {
                 const int sd = wall - 1;
                 if ((sd ? bchi : bclo) == BC_MOVING) {
@@ -503,8 +508,9 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
         T Lx1 = 0, Lx2 = 0;
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
-            const T v = pdec<Q, S, T>(penc<Q, S, T>(s[a], a), a);   // the value as stored
-            pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + (uint32_t)i * sr_b, a, s[a]);
+            const T st = s[a] + tb(TB::SB(a));                                  // storage base
+            const T v = pdec<Q, S, T>(penc<Q, S, T>(st, a), a) - tb(TB::SB(a));  // as stored, compute base
+            pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + (uint32_t)i * sr_b, a, st);
             if (a > 0) {
                 Lx1 += tb(TB::A1(a)) * v;
                 Lx2 += tb(TB::A2(a)) * v;

@@ -418,27 +418,32 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     ta.periodic1 = per1;
     ta.bc_lo = D.bc_lo;
     ta.bc_hi = D.bc_hi;
+    // FP64 stores and computes with the particle numbers themselves; FP32 and
+    // FP16 store offsets from the requested base and compute relative to the
+    // local rest state, whose offsets are the smallest numbers
     ta.base_kind = (D.precision == LBM_FP64) ? 2 : D.offset_base;
+    ta.cbase_kind = (D.precision == LBM_FP64) ? 2 : 0;
     ta.rho0 = D.rho0;
     ta.kpi = -(1.0 - 1.0 / (2.0 * D.tau));
     g->base = (double *)dalloc(g, (size_t)g->nent * q * 8);
+    double *cbase = (double *)dalloc(g, (size_t)g->nent * q * 8);
     g->mB64 = (double *)dalloc(g, (size_t)g->nent * 8);
     const int tabw = q == 9 ? Tab<9>::STRIDE : Tab<21>::STRIDE;
     g->tab = dalloc(g, (size_t)g->nent * tabw * comp_size(g->precision));
-    if (!g->base || !g->mB64 || !g->tab) return bail(LBM_ENOMEM, "device allocation failed (tables)");
+    if (!g->base || !cbase || !g->mB64 || !g->tab) return bail(LBM_ENOMEM, "device allocation failed (tables)");
     const dim3 eb((g->nent + 127) / 128);
     if (q == 9) {
-        hipLaunchKernelGGL(k_base<9>, eb, dim3(128), 0, st, ta, g->base, g->mB64);
+        hipLaunchKernelGGL(k_base<9>, eb, dim3(128), 0, st, ta, g->base, cbase, g->mB64);
         if (g->precision == LBM_FP64)
-            hipLaunchKernelGGL((k_table<9, double>), eb, dim3(128), 0, st, ta, g->base, g->mB64, (double *)g->tab);
+            hipLaunchKernelGGL((k_table<9, double>), eb, dim3(128), 0, st, ta, g->base, cbase, g->mB64, (double *)g->tab);
         else
-            hipLaunchKernelGGL((k_table<9, float>), eb, dim3(128), 0, st, ta, g->base, g->mB64, (float *)g->tab);
+            hipLaunchKernelGGL((k_table<9, float>), eb, dim3(128), 0, st, ta, g->base, cbase, g->mB64, (float *)g->tab);
     } else {
-        hipLaunchKernelGGL(k_base<21>, eb, dim3(128), 0, st, ta, g->base, g->mB64);
+        hipLaunchKernelGGL(k_base<21>, eb, dim3(128), 0, st, ta, g->base, cbase, g->mB64);
         if (g->precision == LBM_FP64)
-            hipLaunchKernelGGL((k_table<21, double>), eb, dim3(128), 0, st, ta, g->base, g->mB64, (double *)g->tab);
+            hipLaunchKernelGGL((k_table<21, double>), eb, dim3(128), 0, st, ta, g->base, cbase, g->mB64, (double *)g->tab);
         else
-            hipLaunchKernelGGL((k_table<21, float>), eb, dim3(128), 0, st, ta, g->base, g->mB64, (float *)g->tab);
+            hipLaunchKernelGGL((k_table<21, float>), eb, dim3(128), 0, st, ta, g->base, cbase, g->mB64, (float *)g->tab);
     }
     HIPB(hipGetLastError());
 
@@ -457,6 +462,7 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     dfree(g, tg);
     dfree(g, geo);
     dfree(g, flag);
+    dfree(g, cbase);
 
     InstDesc &I = g->h_inst;
     I.P[0] = g->P[0];

@@ -116,7 +116,9 @@ __global__ void k_canon_rows(int n1, int n2, double *__restrict__ J, double *__r
 struct TableArgs {
     const double *geo;   // [field][ncell]
     int n1, n2, ncell, cellmode, nent;
-    int periodic1, bc_lo, bc_hi, base_kind;
+    int periodic1, bc_lo, bc_hi;
+    int base_kind;        // storage base of the population offsets (LBM_BASE_*)
+    int cbase_kind;       // base the step computes relative to (0 local rest, 2 none)
     double rho0;
     double kpi;           // -(1 - 1/(2 tau))
 };
@@ -132,9 +134,20 @@ __device__ inline double rest_phi(int a, double G11, double G12, double G22)
     return weight<Q>(a) * (1.0 + (cGc - (c1 * c1 + c2 * c2) - T0 * (G11 + G22 - 2.0)) / (2.0 * T0));
 }
 
-// base B_a per entry (FP64) and its sum
+// base B_a of a given kind at a cell (FP64): 0 the local rest equilibrium
+// J rho0 phi_rest(g^ij), 1 the uniform J w_a rho0, 2 none
 template <int Q>
-__global__ void k_base(TableArgs t, double *__restrict__ base, double *__restrict__ mB64)
+__device__ inline double base_of(int kind, int a, double J, double rho0, double G11, double G12, double G22)
+{
+    if (kind == 0) return J * rho0 * rest_phi<Q>(a, G11, G12, G22);
+    if (kind == 1) return J * rho0 * weight<Q>(a);
+    return 0.0;
+}
+
+// storage base B_a and compute base C_a per entry (FP64), and the compute
+// base's sum (the base mass of the step)
+template <int Q>
+__global__ void k_base(TableArgs t, double *__restrict__ base, double *__restrict__ cbase, double *__restrict__ mB64)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= t.nent) return;
@@ -144,18 +157,17 @@ __global__ void k_base(TableArgs t, double *__restrict__ base, double *__restric
     const double G11 = t.geo[GEO_G11 * nc + c], G12 = t.geo[GEO_G12 * nc + c], G22 = t.geo[GEO_G22 * nc + c];
     double s = 0.0;
     for (int a = 0; a < Q; ++a) {
-        double B = 0.0;
-        if (t.base_kind == 0) B = J * t.rho0 * rest_phi<Q>(a, G11, G12, G22);
-        else if (t.base_kind == 1) B = J * t.rho0 * weight<Q>(a);
-        base[(size_t)e * Q + a] = B;
-        s += B;
+        base[(size_t)e * Q + a] = base_of<Q>(t.base_kind, a, J, t.rho0, G11, G12, G22);
+        const double C = base_of<Q>(t.cbase_kind, a, J, t.rho0, G11, G12, G22);
+        cbase[(size_t)e * Q + a] = C;
+        s += C;
     }
     mB64[e] = s;
 }
 
 template <int Q, typename T>
-__global__ void k_table(TableArgs t, const double *__restrict__ base, const double *__restrict__ mB64,
-                        T *__restrict__ tab)
+__global__ void k_table(TableArgs t, const double *__restrict__ base, const double *__restrict__ cbase,
+                        const double *__restrict__ mB64, T *__restrict__ tab)
 {
     using TB = Tab<Q>;
     constexpr double T0 = lattice_T0<Q>();
@@ -170,7 +182,7 @@ __global__ void k_table(TableArgs t, const double *__restrict__ base, const doub
     };
     const double G11 = t.geo[GEO_G11 * nc + c], G12 = t.geo[GEO_G12 * nc + c], G22 = t.geo[GEO_G22 * nc + c];
     auto A = [&](int a, int comp) { return t.geo[(GEO_A0 + 2 * a + comp) * nc + c]; };
-    const double *B = base + (size_t)e * Q;
+    const double *B = cbase + (size_t)e * Q;     // the step's base at this entry
     const double mB = mB64[e];
     put(TB::G11, G11);
     put(TB::G12, G12);
@@ -198,8 +210,11 @@ __global__ void k_table(TableArgs t, const double *__restrict__ base, const doub
             sj = ((sj % t.n2) + t.n2) % t.n2;
             se = r * t.n2 + sj;
         }
+        // the source's stored offset, moved to this entry's compute base
         put(TB::DB(a), base[(size_t)se * Q + beta] - B[a]);
     }
+    // a stored offset is the computed one plus (compute base - storage base)
+    for (int a = 0; a < Q; ++a) put(TB::SB(a), B[a] - base[(size_t)e * Q + a]);
     for (int p = 0; p < npair<Q>(); ++p) {
         const int a = pair_rep(p);
         const double c1 = cx(a), c2 = cy(a);
@@ -297,7 +312,7 @@ __global__ void k_lag(const InstDesc *__restrict__ d, int pin)
     const S *P = (const S *)d->P[pin];
     T L1 = 0, L2 = 0;
     for (int a = 1; a < Q; ++a) {
-        const T v = pdec<Q, S, T>(P[pidx(d, a, i, j)], a);
+        const T v = pdec<Q, S, T>(P[pidx(d, a, i, j)], a) - tv(TB::SB(a));
         L1 += tv(TB::A1(a)) * v;
         L2 += tv(TB::A2(a)) * v;
     }
