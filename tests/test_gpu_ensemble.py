@@ -51,25 +51,61 @@ def _oracle_stable(rc, seed, horizon=400, rel=1e-9):
     return bool(np.isfinite(d0) and np.isfinite(d1) and d1 <= 10.0 * d0), d0, d1
 
 
-def test_ensemble_batched_fp32_vs_reduced_oracle():
-    cases = G.workload_ensemble()
-    grids = [lbm.Grid(c, precision=lbm.LBM_FP32) for c in cases]
+_ORACLE = {}
+
+
+def _oracle_state(k, c):
+    """Oracle u^theta-related moments of instance k after STEPS steps, and its
+    stability class (cached: the FP32 and FP16 tests share them)."""
+    if k not in _ORACLE:
+        rc = _reduced(c)
+        o = oracle.OracleGrid(rc)
+        o.init(1.0)
+        o.step(STEPS)
+        mo, Uo, Uto = o.moments()
+        _ORACLE[k] = (Uto, _oracle_stable(rc, seed=k))
+    return _ORACLE[k]
+
+
+def _run_batched(cases, prec):
+    grids = [lbm.Grid(c, precision=prec) for c in cases]
     for g in grids:
         g.init()
     b = lbm.lbm_batch_create([g.h for g in grids])
     lbm.lbm_batch_step(b, STEPS)
     recs = lbm.lbm_batch_residuals(b, len(grids))
     lbm.lbm_batch_destroy(b)
+    return grids, recs
+
+
+def test_ensemble_batched_fp16_error_stated():
+    """FP16 storage (offsets scaled by 1/w per direction plane) on the whole
+    ensemble: the error against the oracle is printed per instance and
+    bounded loosely; FP16 rounding (about 5e-4 relative) sets it."""
+    cases = G.workload_ensemble()
+    grids, recs = _run_batched(cases, lbm.LBM_FP16)
+    errs = []
+    for k, (c, g, r) in enumerate(zip(cases, grids, recs)):
+        Uto, (stable, d0, d1) = _oracle_state(k, c)
+        if not stable:
+            continue
+        assert r.bad_cells == 0, k
+        m, U, Ut = g.moments()
+        col = Ut.reshape(c.n1, c.n2, 2)[:, 0]
+        errs.append(np.abs((col[:, 1] - Uto[:, 1]) * c.meta["centres"] * np.sin(c.meta["dtheta"])).max() / 0.05)
+    errs = np.array(errs)
+    say("ensemble FP16: %d stable instances, u_theta err / U median %.2e, max %.2e" % (len(errs), np.median(errs), errs.max()))
+    assert errs.max() <= 5e-3
+
+
+def test_ensemble_batched_fp32_vs_reduced_oracle():
+    cases = G.workload_ensemble()
+    grids, recs = _run_batched(cases, lbm.LBM_FP32)
     worst, checked, unstable = 0.0, 0, []
     for k, (c, g, r) in enumerate(zip(cases, grids, recs)):
-        rc = _reduced(c)
-        o = oracle.OracleGrid(rc)
-        o.init(1.0)
-        o.step(STEPS)
-        mo, Uo, Uto = o.moments()
+        Uto, (stable, d0, d1) = _oracle_state(k, c)
         ok_o = np.isfinite(Uto).all()
         assert ok_o == (r.bad_cells == 0), k
-        stable, d0, d1 = _oracle_stable(rc, seed=k)
         if not stable:
             unstable.append(k)
             say("instance %d unstable in the oracle (Q%d, %dx%d, tau %.3f): perturbation %.1e -> %.1e"
