@@ -180,6 +180,22 @@ int lbm_noflow_adjust(lbm_grid *g, double tol, int64_t max_steps, int32_t check_
 int lbm_get_state(lbm_grid *g, double *P, double *side);
 int lbm_set_state(lbm_grid *g, const double *P, const double *side);
 
+/* Checkpoint blob (host memory, owned by the caller): a header (lattice,
+ * shape, storage precision of the writer, step count) followed by the FP64
+ * state of lbm_get_state.  lbm_save with buf = NULL stores the required size
+ * in *len; otherwise *len must be at least that size (LBM_EINVAL) and
+ * receives the bytes written.  lbm_load restores the state into a grid of the
+ * same lattice and shape (LBM_EINVAL otherwise), in any storage precision,
+ * and resets the step count; the grid must have been created (not
+ * necessarily initialised).  Both synchronise. */
+int lbm_save(lbm_grid *g, void *buf, size_t *len);
+int lbm_load(lbm_grid *g, const void *buf, size_t len);
+
+/* Physical velocity Ut^i g_i per cell (Sec. 2; the velocity the paper's
+ * profiles show): u[n1*n2][2] = (x, y) components, FP64, from the same
+ * moments as lbm_moments.  Synchronises. */
+int lbm_physical_velocity(lbm_grid *g, double *u);
+
 /* Streaming map actually used by the step kernel: for every cell and
  * direction, the source cell (i*n2 + j), source direction and crossed wall
  * (0 none, 1 low, 2 high).  Arrays [n1*n2][q].  Synchronises. */

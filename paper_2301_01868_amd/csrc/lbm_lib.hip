@@ -811,6 +811,99 @@ int lbm_moments(lbm_grid *g, double *m, double *U, double *Ut)
     return LBM_OK;
 }
 
+int lbm_physical_velocity(lbm_grid *g, double *u)
+{
+    if (!g || !u) return fail(g, LBM_EINVAL, "null argument");
+    if (!g->inited) return fail(g, LBM_ESTATE, "lbm_init must be called first");
+    int rc = run_moments(g);
+    if (rc != LBM_OK) return rc;
+    const size_t nc = g->ncell;
+    double *d = (double *)dalloc(g, nc * 2 * 8);
+    if (!d) return fail(g, LBM_ENOMEM, "allocation failed");
+    hipLaunchKernelGGL(k_physical_velocity, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, g->stream, g->mom, g->g4,
+                       (int)nc, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(u, d, nc * 2 * 8, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    dfree(g, d);
+    if (e != hipSuccess) return fail(g, LBM_EDEVICE, std::string("physical velocity: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+namespace {
+// checkpoint blob: header, then P[q][n1][n2] and side[2][2][c_max][n2] (FP64)
+struct CkptHeader {
+    char magic[8];
+    int32_t q, n1, n2, precision;
+    int64_t step;
+    double mass0;        // mass at lbm_init (drift reference)
+    int64_t nP, nside;
+};
+const char CKPT_MAGIC[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
+} // namespace
+
+static size_t ckpt_counts(const lbm_grid *g, int64_t *nP, int64_t *nside)
+{
+    *nP = (int64_t)g->q * g->ncell;
+    *nside = (int64_t)4 * g->hw * g->n2;
+    return sizeof(CkptHeader) + (size_t)(*nP + *nside) * sizeof(double);
+}
+
+int lbm_save(lbm_grid *g, void *buf, size_t *len)
+{
+    if (!g || !len) return fail(g, LBM_EINVAL, "null argument");
+    int64_t nP, ns;
+    const size_t need = ckpt_counts(g, &nP, &ns);
+    if (!buf) {
+        *len = need;
+        return LBM_OK;
+    }
+    if (*len < need) return fail(g, LBM_EINVAL, "checkpoint buffer too small");
+    if (!g->inited) return fail(g, LBM_ESTATE, "lbm_init must be called first");
+    CkptHeader h{};
+    std::memcpy(h.magic, CKPT_MAGIC, 8);
+    h.q = g->q;
+    h.n1 = g->n1;
+    h.n2 = g->n2;
+    h.precision = g->precision;
+    h.step = g->step;
+    h.mass0 = g->mass0;
+    h.nP = nP;
+    h.nside = ns;
+    std::memcpy(buf, &h, sizeof h);
+    double *P = (double *)((char *)buf + sizeof h);
+    const int rc = lbm_get_state(g, P, P + nP);
+    if (rc != LBM_OK) return rc;
+    *len = need;
+    return LBM_OK;
+}
+
+int lbm_load(lbm_grid *g, const void *buf, size_t len)
+{
+    if (!g || !buf) return fail(g, LBM_EINVAL, "null argument");
+    int64_t nP, ns;
+    const size_t need = ckpt_counts(g, &nP, &ns);
+    CkptHeader h{};
+    if (len < sizeof h) return fail(g, LBM_EINVAL, "checkpoint too short");
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0) return fail(g, LBM_EINVAL, "not a checkpoint of this library");
+    if (h.q != g->q || h.n1 != g->n1 || h.n2 != g->n2 || h.nP != nP || h.nside != ns)
+        return fail(g, LBM_EINVAL, "checkpoint lattice or grid shape differs from the grid's");
+    if (len < need) return fail(g, LBM_EINVAL, "checkpoint truncated");
+    const double *P = (const double *)((const char *)buf + sizeof h);
+    int rc = lbm_set_state(g, P, P + nP);
+    if (rc != LBM_OK) return rc;
+    g->step = h.step;
+    // residual snapshot at the restored step; drift keeps the writer's reference
+    double r[RED_NF];
+    rc = reduce(g, 1, r);
+    if (rc != LBM_OK) return rc;
+    g->mass0 = h.mass0 > 0.0 ? h.mass0 : r[0];
+    g->snap_valid = true;
+    g->snap_step = g->step;
+    return LBM_OK;
+}
+
 int lbm_noflow_adjust(lbm_grid *g, double tol, int64_t max_steps, int32_t check_every, int64_t *steps_out)
 {
     if (!g) return fail(nullptr, LBM_EINVAL, "null grid");

@@ -387,6 +387,18 @@ __global__ void k_stream_map(const InstDesc *__restrict__ d, int *__restrict__ s
     }
 }
 
+// physical velocity u = Ut^1 g_1 + Ut^2 g_2 (FP64) from the moments [5][n]
+// and the tangent basis [4][n]; out[n][2] = (x, y)
+__global__ void k_physical_velocity(const double *__restrict__ mom, const double *__restrict__ g4, int n,
+                                    double *__restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const double u1 = mom[3 * (size_t)n + c], u2 = mom[4 * (size_t)n + c];
+    out[2 * (size_t)c] = u1 * g4[c] + u2 * g4[2 * (size_t)n + c];
+    out[2 * (size_t)c + 1] = u1 * g4[(size_t)n + c] + u2 * g4[3 * (size_t)n + c];
+}
+
 // J' = m / rho0
 __global__ void k_volume_from_mass(const double *__restrict__ m, double rho0, int n, double *__restrict__ J)
 {

@@ -24,7 +24,7 @@ BC = {"periodic": LBM_PERIODIC, "noslip": LBM_NOSLIP, "moving": LBM_MOVING}
 
 EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_error", "lbm_grid_info_get",
             "lbm_set_volume", "lbm_get_volume", "lbm_init", "lbm_step", "lbm_moments", "lbm_residual", "lbm_noflow_adjust",
-            "lbm_get_state", "lbm_set_state", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
+            "lbm_get_state", "lbm_set_state", "lbm_save", "lbm_load", "lbm_physical_velocity", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
             "lbm_stream", "lbm_batch_create", "lbm_batch_create_ex", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_set_occupancy", "lbm_autotune",
             "lbm_copy_probe", "lbm_bandwidth_probe"]
 
@@ -94,6 +94,9 @@ def load():
     L.lbm_noflow_adjust.argtypes = [vp, ct.c_double, ct.c_int64, ct.c_int32, ct.POINTER(ct.c_int64)]
     L.lbm_get_state.argtypes = [vp, D, D]
     L.lbm_set_state.argtypes = [vp, D, D]
+    L.lbm_save.argtypes = [vp, vp, ct.POINTER(ct.c_size_t)]
+    L.lbm_load.argtypes = [vp, vp, ct.c_size_t]
+    L.lbm_physical_velocity.argtypes = [vp, D]
     L.lbm_stream_map.argtypes = [vp, I32, I32, I32]
     L.lbm_geometry.argtypes = [vp, D]
     L.lbm_synchronize.argtypes = [vp]
@@ -264,6 +267,26 @@ def lbm_set_occupancy(h, waves_per_cu):
     _chk(load().lbm_set_occupancy(h, int(waves_per_cu)), h)
 
 
+def lbm_save(h):
+    """Checkpoint blob of the grid's state (bytes)."""
+    n = ct.c_size_t(0)
+    _chk(load().lbm_save(h, None, ct.byref(n)), h)
+    buf = ct.create_string_buffer(n.value)
+    _chk(load().lbm_save(h, buf, ct.byref(n)), h)
+    return buf.raw[:n.value]
+
+
+def lbm_load(h, blob):
+    buf = ct.create_string_buffer(bytes(blob), len(blob))
+    _chk(load().lbm_load(h, buf, len(blob)), h)
+
+
+def lbm_physical_velocity(h, ncell):
+    u = np.zeros((ncell, 2))
+    _chk(load().lbm_physical_velocity(h, _dp(u)), h)
+    return u
+
+
 def lbm_batch_create(handles):
     arr = (ct.c_void_p * len(handles))(*[h.value if isinstance(h, ct.c_void_p) else h for h in handles])
     b = ct.c_void_p()
@@ -372,6 +395,15 @@ class Grid:
 
     def noflow_adjust(self, tol=1e-12, max_steps=10 ** 7, check_every=1000):
         return lbm_noflow_adjust(self.h, tol, max_steps, check_every)
+
+    def save(self):
+        return lbm_save(self.h)
+
+    def load(self, blob):
+        lbm_load(self.h, blob)
+
+    def physical_velocity(self):
+        return lbm_physical_velocity(self.h, self.ncell)
 
     def get_state(self):
         return lbm_get_state(self.h, self.q, self.n1, self.n2, self.cmax)

@@ -154,3 +154,33 @@ def test_batch_with_fixed_point_force_grids():
         assert np.array_equal(ga.get_state()[0], gm.get_state()[0])
     # the fixed-point passes change the result
     assert not np.array_equal(mixed[0].get_state()[0], mixed[1].get_state()[0])
+
+
+@pytest.mark.parametrize("prec", [lbm.LBM_FP64, lbm.LBM_FP32], ids=["fp64", "fp32"])
+def test_checkpoint_blob_resume(prec):
+    """lbm_save / lbm_load: a grid restored from the blob into a fresh grid
+    continues exactly as the original does; metadata is checked."""
+    case = G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, u_outer=-0.02, tau=0.8)
+    a = lbm.Grid(case, precision=prec)
+    a.init()
+    a.step(57)
+    blob = a.save()
+    b = lbm.Grid(case, precision=prec)
+    b.load(blob)
+    assert b.info.step == a.info.step == 57
+    a.step(40)
+    b.step(40)
+    assert np.array_equal(a.get_state()[0], b.get_state()[0])
+    assert np.array_equal(a.get_state()[1], b.get_state()[1])
+    ra, rb = a.residual(), b.residual()
+    assert ra.mass_rel_drift == rb.mass_rel_drift
+    # a blob loads into any storage precision of the same lattice and shape
+    c = lbm.Grid(case, precision=lbm.LBM_FP64 if prec == lbm.LBM_FP32 else lbm.LBM_FP32)
+    c.load(blob)
+    # and is refused by a grid of another shape
+    other = lbm.Grid(G.circular_couette(21, 12, 96, 10.0, u_inner=0.05, tau=0.8), precision=prec)
+    with pytest.raises(lbm.LbmError) as e:
+        other.load(blob)
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError):
+        b.load(b"not a checkpoint" * 4)

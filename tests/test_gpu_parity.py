@@ -168,3 +168,15 @@ def test_noflow_adjust_matches_oracle_procedure():
     mo, _, _ = o.moments()
     # J' = m_nf / rho0 from the same number of no-flow steps
     assert norm_rel(g.get_volume(), mo / case.rho0) <= 1e-11
+
+
+@pytest.mark.parametrize("name,case", CASES, ids=[c[0] for c in CASES])
+def test_physical_velocity_matches_oracle(name, case):
+    """Ut^i g_i per cell (the velocity the paper's profiles show)."""
+    g, o = pair(case)
+    g.step(40)
+    o.step(40)
+    u = g.physical_velocity()
+    mo, Uo, Uto = o.moments()
+    uo = o.physical_velocity(Uto)
+    assert np.abs(u - uo).max() <= 1e-12 * max(np.abs(uo).max(), 1e-3)
