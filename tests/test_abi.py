@@ -88,3 +88,29 @@ def test_null_arguments_are_rejected(lib):
     assert lib.lbm_init(None, None) == lbm.LBM_EINVAL
     assert lib.lbm_step(None, ct.c_int64(1)) == lbm.LBM_EINVAL
     assert lib.lbm_set_occupancy(None, 0) == lbm.LBM_EINVAL
+
+
+def test_header_is_c_and_links_from_c(lib, tmp_path):
+    """include/lbm.h compiles as strict C99 and the library links from C; the
+    host-only lattice call runs without a GPU."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include "lbm.h"\n#include <stdio.h>\n'
+        "int main(void) {\n"
+        "    int32_t cx[21], cy[21]; double w[21], T0 = 0.0;\n"
+        "    lbm_grid_desc d = {0}; lbm_resid r = {0}; lbm_grid_info info = {0};\n"
+        "    (void)d; (void)r; (void)info;\n"
+        "    if (lbm_lattice(21, cx, cy, w, &T0) != LBM_OK) return 1;\n"
+        "    if (lbm_lattice(15, cx, cy, w, &T0) != LBM_EINVAL) return 2;\n"
+        '    printf("%.17g %d %d\\n", T0, cx[17], cy[18]);\n'
+        "    return 0;\n}\n")
+    exe = tmp_path / "abi"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                           os.path.join(ROOT, "include"), "-o", str(exe), str(src), lbm.LIB_PATH,
+                           "-Wl,-rpath," + os.path.dirname(lbm.LIB_PATH)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert float(out[0]) == 2.0 / 3.0 and out[1:] == ["3", "3"]
