@@ -64,10 +64,15 @@ enum {
     LBM_BASE_NONE = 2        /* B = 0 (always used for LBM_FP64) */
 };
 
-/* geometry table mode */
+/* geometry table mode (Sec. 2: the metric terms of the step, Eqs. metric,
+ * covectors and gamma, per row of the grid or per cell) */
 enum {
-    LBM_GEOM_AUTO = 0,  /* per-row tables when the metric terms do not depend on q2 */
-    LBM_GEOM_CELL = 1   /* per-cell tables (general mappings) */
+    LBM_GEOM_AUTO = 0,       /* per-row tables when the metric terms do not depend on q2,
+                                else as LBM_GEOM_CELL */
+    LBM_GEOM_CELL = 1,       /* per cell, rebuilt in the step from the FP64 geometry of the cell
+                                and its neighbours (staged in LDS; 32 or 64 B per cell) */
+    LBM_GEOM_CELL_TABLE = 2  /* per cell, read from a stored table of every term (4Q + 3 values
+                                and more per cell) */
 };
 
 typedef struct lbm_grid lbm_grid;
@@ -96,7 +101,7 @@ typedef struct {
     int32_t offset_base;    /* LBM_BASE_* (ignored for LBM_FP64) */
     int32_t iterations;     /* 0: force with the lagged N'(q, t-1) (Sec. 2); k > 0: k extra
                                fixed-point passes of the implicit force relation */
-    int32_t geometry;       /* LBM_GEOM_AUTO | LBM_GEOM_CELL */
+    int32_t geometry;       /* LBM_GEOM_AUTO | LBM_GEOM_CELL | LBM_GEOM_CELL_TABLE */
     const lbm_allocator *alloc; /* NULL: hipMalloc/hipFree */
     void *stream;           /* hipStream_t for all work on this grid; NULL: the library makes one */
 } lbm_grid_desc;
@@ -124,6 +129,9 @@ typedef struct {
     size_t device_bytes;           /* device memory held by the grid */
     int32_t waves_per_block;       /* step launch: waves (rows of 64 cells) per workgroup */
     int32_t waves_per_cu_cap;      /* step launch: resident waves per CU cap, 0 = none */
+    int32_t table_kind;            /* 0 per-row tables, 1 per-cell tables, 2 per-cell terms
+                                      rebuilt from the geometry in the step */
+    int32_t reserved;
 } lbm_grid_info;
 
 /* Lattice tables of App. A / App. B (host only): velocities cx[q], cy[q],

@@ -83,8 +83,15 @@ struct InstDesc {
     long long lsa, lsr;  // the same for the two force-sum fields of a lag buffer
     int n1, n2, pitch, hw;
     int periodic1, bc_lo, bc_hi, cell;
-    int iters, ncell, par0, pad;
-    double ut_lo, ut_hi, a1, a2, omega, kpi;
+    int iters, ncell, par0;
+    int sbase;           // storage base kind of the population offsets (0 local rest, 1 J w rho0, 2 none)
+    double ut_lo, ut_hi, a1, a2, omega, kpi, rho0;
+    // per-cell geometry for steps that rebuild their table fields (GE_* fields,
+    // FP64, [field][n1 + 2 c_max][n2 + 2 c_max]: the cells and c_max layers of
+    // the mapping's continuation around them)
+    const double *geo;
+    long long gfs;       // element stride between fields
+    int gw, gpad;        // row width n2 + 2 c_max
 };
 
 // Element index of population a of cell (i, j) in a population buffer.  Each
@@ -235,12 +242,320 @@ struct TabView {
 };
 
 // ---------------------------------------------------------------------------
+// Per-cell table fields rebuilt from the geometry (general mappings).  A grid
+// whose metric terms depend on q2 can step without a stored per-cell table:
+// the workgroup stages the FP64 tangents g_1, g_2 of its cells and of c_max
+// layers around them (and, for offset storage, J and H = J g^ij) into LDS,
+// and every field of Tab<Q> is evaluated where the step uses it, from the
+// cell's own geometry and that of q + c_a, q - c_a or the pulled source:
+//   A+^i_a(q) = g^i(q) . [e_a(q + c_a) - e_a(q)],  e_a = c^1_a g_1 + c^2_a g_2   (Eq. gamma)
+//   S^i_a = A+^i_a + A+^i_{-a} = g^i(q) . [e_a(q + c_a) - e_a(q - c_a)]
+// The differences of neighbouring tangents are taken in FP64, so the
+// Christoffel sums keep the relative accuracy of the compute type where the
+// mapping varies slowly.  The base terms of offset storage come from the local
+// rest state, linear in (J, H) and evaluated in FP64:
+//   J phi_rest,a = w_a [(2 - |c_a|^2 / (2 T0)) J + (c_a.H.c_a - T0 tr H) / (2 T0)]
+// ---------------------------------------------------------------------------
+enum { GE_G1X = 0, GE_G1Y, GE_G2X, GE_G2Y, GE_J, GE_H11, GE_H12, GE_H22, GE_NF };
+
+// geometry fields a step of compute type T stages: the tangents, plus J and H
+// where populations are offsets from the local rest state (FP32 compute)
+template <typename T>
+__host__ __device__ constexpr int geo_stage_fields()
+{
+    return sizeof(T) == 4 ? GE_NF : GE_J;
+}
+// LDS bytes of one workgroup's staged geometry (wpb rows of 64 cells)
+template <int Q, typename T>
+__host__ __device__ constexpr unsigned geo_stage_bytes(int wpb)
+{
+    return (unsigned)(geo_stage_fields<T>() * (wpb + 2 * cmax<Q>()) * (64 + 2 * cmax<Q>()) * sizeof(double));
+}
+
+// rho0-free local rest state J phi_rest of direction a; s = -1 reflects the
+// q1 component of c_a (specular source direction), which flips the c1 c2 term
+template <int Q>
+__device__ inline double jrest(int a, double J, double h11, double h12, double h22, double s = 1.0)
+{
+    constexpr double T0 = lattice_T0<Q>();
+    const double c1 = cx(a), c2 = cy(a);
+    const double cc = c1 * c1 + c2 * c2;
+    return weight<Q>(a) * ((2.0 - cc / (2.0 * T0)) * J +
+                           (c1 * c1 * h11 + 2.0 * s * c1 * c2 * h12 + c2 * c2 * h22 - T0 * (h11 + h22)) * (1.0 / (2.0 * T0)));
+}
+
+// Copy the geometry of the workgroup's rows tl.y .. tl.y + wpb - 1 and columns
+// tl.z .. tl.z + 63, with c_max layers around them, into LDS
+// [field][wpb + 2 c_max][64 + 2 c_max].  Entries outside the stored range
+// (rows or columns past the grid's continuation) are zero and never read by a
+// cell inside the grid.
+template <int Q, typename T>
+__device__ __forceinline__ const double *stage_geometry(const InstDesc *__restrict__ d, const int4 tl, int wave)
+{
+    extern __shared__ double geo_lds[];
+    constexpr int CM = cmax<Q>(), TC = 64 + 2 * CM;
+    constexpr int NF = geo_stage_fields<T>();
+    const int nw = (int)(blockDim.x >> 6), TR = nw + 2 * CM;
+    const int lane = (int)(threadIdx.x & 63);
+    const int ger = d->n1 + 2 * CM, gw = d->gw;
+    const double *__restrict__ ge = d->geo;
+    // each wave copies tile rows (one field, one row of 64 + 2 c_max cells),
+    // U rows per pass with all loads issued before the stores
+    constexpr int U = 4;
+    for (int row0 = wave; row0 < NF * TR; row0 += U * nw) {
+        double v[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int row = row0 + u * nw;
+            const int f = row / TR, rr = row - f * TR;
+            const int er = tl.y + rr;
+            const double *src = ge + (size_t)f * d->gfs + (size_t)er * gw + tl.z;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cc = lane + 64 * h;
+                v[u][h] = (row < NF * TR && cc < TC && er < ger && tl.z + cc < gw) ? src[cc] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int row = row0 + u * nw;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cc = lane + 64 * h;
+                if (row < NF * TR && cc < TC) geo_lds[row * TC + cc] = v[u][h];
+            }
+        }
+    }
+    __syncthreads();
+    return geo_lds;
+}
+
+template <int Q, typename T>
+struct GeoTab {
+    using TB = Tab<Q>;
+    static constexpr int CM = cmax<Q>();
+    static constexpr double T0 = lattice_T0<Q>();
+    // offsets: compute relative to the local rest state (FP32 compute), else
+    // with the particle numbers themselves (FP64)
+    static constexpr bool CB = sizeof(T) == 4;
+    const double *L;   // staged geometry
+    int o, tc, fs;     // own cell in a staged field, row stride, field stride
+    int i, n1, per1, bclo, bchi, sbase;
+    double g1x, g1y, g2x, g2y, J, h11, h12, h22, rho0;
+    T u1x, u1y, u2x, u2y, G11, G12, G22, mb, c1s, c2s, kpi;
+
+    __device__ __forceinline__ double ld(int f, int dr, int dc) const { return L[f * fs + o + dr * tc + dc]; }
+
+    // e_a(q + c_a) - e_a(q)
+    __device__ __forceinline__ void dA(int a, double &dx, double &dy) const
+    {
+        const int c1 = cx(a), c2 = cy(a);
+        dx = 0.0;
+        dy = 0.0;
+        if (c1 != 0) {
+            dx += c1 * (ld(GE_G1X, c1, c2) - g1x);
+            dy += c1 * (ld(GE_G1Y, c1, c2) - g1y);
+        }
+        if (c2 != 0) {
+            dx += c2 * (ld(GE_G2X, c1, c2) - g2x);
+            dy += c2 * (ld(GE_G2Y, c1, c2) - g2y);
+        }
+    }
+    // e_a(q + c_a) - e_a(q - c_a)
+    __device__ __forceinline__ void dS(int a, double &dx, double &dy) const
+    {
+        const int c1 = cx(a), c2 = cy(a);
+        dx = 0.0;
+        dy = 0.0;
+        if (c1 != 0) {
+            dx += c1 * (ld(GE_G1X, c1, c2) - ld(GE_G1X, -c1, -c2));
+            dy += c1 * (ld(GE_G1Y, c1, c2) - ld(GE_G1Y, -c1, -c2));
+        }
+        if (c2 != 0) {
+            dx += c2 * (ld(GE_G2X, c1, c2) - ld(GE_G2X, -c1, -c2));
+            dy += c2 * (ld(GE_G2Y, c1, c2) - ld(GE_G2Y, -c1, -c2));
+        }
+    }
+
+    __device__ __forceinline__ void setup(const InstDesc *__restrict__ d, const double *lds, int nw, int wave, int lane,
+                                          int row, int col)
+    {
+        L = lds;
+        tc = 64 + 2 * CM;
+        fs = (nw + 2 * CM) * tc;
+        o = (wave + CM) * tc + lane + CM;
+        i = row;
+        n1 = d->n1;
+        per1 = d->periodic1;
+        bclo = d->bc_lo;
+        bchi = d->bc_hi;
+        sbase = d->sbase;
+        rho0 = d->rho0;
+        kpi = (T)d->kpi;
+        g1x = ld(GE_G1X, 0, 0);
+        g1y = ld(GE_G1Y, 0, 0);
+        g2x = ld(GE_G2X, 0, 0);
+        g2y = ld(GE_G2Y, 0, 0);
+        double iJ;
+        if constexpr (CB) {
+            J = ld(GE_J, 0, 0);
+            h11 = ld(GE_H11, 0, 0);
+            h12 = ld(GE_H12, 0, 0);
+            h22 = ld(GE_H22, 0, 0);
+            iJ = 1.0 / J;
+            G11 = (T)(h11 * iJ);
+            G12 = (T)(h12 * iJ);
+            G22 = (T)(h22 * iJ);
+        } else {
+            J = g1x * g2y - g1y * g2x;
+            iJ = 1.0 / J;
+            const double iJ2 = iJ * iJ;
+            h11 = h12 = h22 = 0.0;
+            G11 = (T)((g2x * g2x + g2y * g2y) * iJ2);
+            G12 = (T)(-(g1x * g2x + g1y * g2y) * iJ2);
+            G22 = (T)((g1x * g1x + g1y * g1y) * iJ2);
+        }
+        // co-tangents g^1 = (g_2 x z) / J, g^2 = (z x g_1) / J
+        const double v1x = g2y * iJ, v1y = -g2x * iJ, v2x = -g1y * iJ, v2y = g1x * iJ;
+        u1x = (T)v1x;
+        u1y = (T)v1y;
+        u2x = (T)v2x;
+        u2y = (T)v2y;
+        mb = (T)0;
+        c1s = (T)0;
+        c2s = (T)0;
+        if constexpr (CB) {
+            // the base's share of the force sum, sum_a (A+_a + A+_-a) B_a,
+            // sums products of population-size bases: formed in FP64 when the
+            // grid is created, read from the grid's per-cell table
+            mb = (T)(rho0 * J);
+            const T *tab = (const T *)d->tab + (size_t)row * d->n2 + col;
+            c1s = tab[(size_t)TB::C1 * d->ncell];
+            c2s = tab[(size_t)TB::C2 * d->ncell];
+        }
+    }
+
+    // rest equilibrium phi_rest,a(g^ij)
+    __device__ __forceinline__ T rest(int a) const
+    {
+        const T c1 = (T)cx(a), c2 = (T)cy(a);
+        const T cGc = c1 * c1 * G11 + (T)2 * c1 * c2 * G12 + c2 * c2 * G22;
+        return (T)weight<Q>(a) *
+               ((T)1 + (cGc - (c1 * c1 + c2 * c2) - (T)T0 * (G11 + G22 - (T)2)) * (T)(1.0 / (2.0 * T0)));
+    }
+    // odd equilibrium coefficient K_a = w_a (c.G.c - T0 tr G) / (2 T0^2)
+    __device__ __forceinline__ T kodd(int a) const
+    {
+        const T c1 = (T)cx(a), c2 = (T)cy(a);
+        const T cGc = c1 * c1 * G11 + (T)2 * c1 * c2 * G12 + c2 * c2 * G22;
+        return (T)(weight<Q>(a) / (2.0 * T0 * T0)) * (cGc - (T)T0 * (G11 + G22));
+    }
+    // storage base of the pulled source, moved to this cell's compute base
+    __device__ __forceinline__ T dbase(int a) const
+    {
+        if constexpr (!CB) {
+            return (T)0;
+        } else {
+            const int ti = i - cx(a);
+            const bool lo = ti < 0, hi = ti >= n1;
+            int dr = -cx(a);
+            double s = 1.0;
+            if (!per1 && (lo || hi)) {
+                // mirror image across the wall: source row r, direction
+                // reversed (no-slip) or with its q1 component flipped (moving)
+                const int r = lo ? -1 - ti : 2 * n1 - 1 - ti;
+                dr = r - i;
+                if ((lo ? bclo : bchi) != BC_NOSLIP) s = -1.0;
+            }
+            const int dc = -cy(a);
+            const double Js = ld(GE_J, dr, dc);
+            const double Bs = sbase == 0 ? jrest<Q>(a, Js, ld(GE_H11, dr, dc), ld(GE_H12, dr, dc), ld(GE_H22, dr, dc), s)
+                                         : weight<Q>(a) * Js;
+            return (T)(rho0 * (Bs - jrest<Q>(a, J, h11, h12, h22)));
+        }
+    }
+    // compute base minus storage base (added to a computed offset to store it)
+    __device__ __forceinline__ T sbdiff(int a) const
+    {
+        if constexpr (!CB) {
+            return (T)0;
+        } else {
+            if (sbase == 0) return (T)0;
+            return (T)(rho0 * (jrest<Q>(a, J, h11, h12, h22) - weight<Q>(a) * J));
+        }
+    }
+
+    __device__ __forceinline__ T operator()(int f) const
+    {
+        if (f == TB::G11) return G11;
+        if (f == TB::G12) return G12;
+        if (f == TB::G22) return G22;
+        if (f == TB::MB) return mb;
+        if (f == TB::C1) return c1s;
+        if (f == TB::C2) return c2s;
+        if (f == TB::D0) return CB ? (T)0 : rest(0);
+        if (f == TB::PHIB0) return CB ? rest(0) : (T)0;
+        if (f < TB::PB(0)) {
+            const int a = (f - 8) / 3 + 1, k = (f - 8) % 3;
+            if (k == 2) return dbase(a);
+            double dx, dy;
+            dA(a, dx, dy);
+            return k == 0 ? (T)dx * u1x + (T)dy * u1y : (T)dx * u2x + (T)dy * u2y;
+        }
+        if (f < TB::SB(0)) {
+            const int p = (f - TB::PB(0)) / 6, k = (f - TB::PB(0)) % 6;
+            const int a = pair_rep(p);
+            if (k == 0) return kodd(a);
+            if (k == 1) return CB ? (T)0 : rest(a);
+            if (k == 2) return CB ? rest(a) : (T)0;
+            double sx, sy;
+            dS(a, sx, sy);
+            const T S1 = (T)sx * u1x + (T)sy * u1y, S2 = (T)sx * u2x + (T)sy * u2y;
+            const T c1 = (T)cx(a), c2 = (T)cy(a);
+            if (k == 3) return kpi * c1 * S1;
+            if (k == 4) return kpi * (c1 * S2 + c2 * S1);
+            return kpi * c2 * S2;
+        }
+        return sbdiff(f - TB::SB(0));
+    }
+};
+
+// Per-lane table fields (stored per-cell tables, or fields rebuilt from the
+// staged geometry) are cheap to read again but costly to keep: without a
+// fence between the phases of the step the compiler holds every field it has
+// read until its last use, over a hundred extra VGPRs for D2Q21.  The fence
+// (a compiler barrier on memory, no instruction) makes it read them again.
+template <int CT>
+__device__ __forceinline__ void phase_fence()
+{
+    if constexpr (CT != 0) __asm__ volatile("" ::: "memory");
+}
+
+// Scheduling boundary between the directions of a loop over per-lane table
+// fields: the scheduler would otherwise start every field's loads at once.
+template <int CT>
+__device__ __forceinline__ void sgroup()
+{
+    if constexpr (CT != 0) __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int Q, typename T, int CT>
+struct TabSel {
+    using type = TabView<T, CT == 1>;
+};
+template <int Q, typename T>
+struct TabSel<Q, T, 2> {
+    using type = GeoTab<Q, T>;
+};
+
+// ---------------------------------------------------------------------------
 // the fused step (pull + moments + force + equilibrium + flux correction +
 // curvilinear correction + BGK + store), one cell per lane, one row segment of
 // 64 columns per wave; MOM = true computes and writes the moments instead of
-// colliding.
+// colliding.  CT: 0 per-row tables, 1 per-cell tables, 2 per-cell fields
+// rebuilt from the staged geometry.
 // ---------------------------------------------------------------------------
-template <int Q, typename T, typename S, bool CELL, bool MOM, bool ITER>
+template <int Q, typename T, typename S, int CT, bool MOM, bool ITER>
 __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, const int4 tl, int par)
 {
     constexpr int CM = cmax<Q>();
@@ -252,6 +567,11 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int i = tl.y + wave;
     const int n1 = d->n1, n2 = d->n2;
+    const double *geo_lds = nullptr;
+    if constexpr (CT == 2) {
+        if (tl.y >= n1) return;   // padding tile (the whole workgroup)
+        geo_lds = stage_geometry<Q, T>(d, tl, wave);
+    }
     if (i >= n1) return;
     const int j0 = tl.z;
     const int j = j0 + (int)(threadIdx.x & 63);
@@ -262,8 +582,10 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
     const int pin = (par ^ d->par0) & 1;
     const int bclo = d->bc_lo, bchi = d->bc_hi, per1 = d->periodic1;
 
-    TabView<T, CELL> tb;
-    if constexpr (CELL) {
+    typename TabSel<Q, T, CT>::type tb;
+    if constexpr (CT == 2) {
+        tb.setup(d, geo_lds, (int)(blockDim.x >> 6), wave, j - j0, i, j);
+    } else if constexpr (CT == 1) {
         tb.p = (const T *)d->tab + (size_t)i * n2 + j;
         tb.s = d->ncell;
     } else {
@@ -304,7 +626,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
                 const uint32_t soff = (uint32_t)a * sa_b + (uint32_t)(i - cx(a)) * sr_b + blk;
                 n[a] = pload<Q, S, T>(rin, vsh[cy(a) + CM], soff, a);
                 // to this cell's compute base (the rest direction pulls from the cell itself)
-                n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
+                if constexpr (CT == 0) n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             }
         } else {
             // one block per row: the column shift rides in the scalar offset
@@ -313,7 +635,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
                 const uint32_t soff = (uint32_t)((int)(a * sa_b + (i - cx(a)) * sr_b) - cy(a) * (int)ES);
                 n[a] = pload<Q, S, T>(rin, jb, soff, a);
                 // to this cell's compute base (the rest direction pulls from the cell itself)
-                n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
+                if constexpr (CT == 0) n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             }
         }
     } else {
@@ -335,7 +657,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             pull_source(i, a, n1, per1, bclo, bchi, r, beta, wall);
             const uint32_t cb = colb[c2 + CM];
             T v = pload<Q, S, T>(rin, cb, (uint32_t)beta * sa_b + (uint32_t)r * sr_b, a);
-            v += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
+            if constexpr (CT == 0) v += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             if (c2 != 0 && wall != 0) {
                 const int sd = wall - 1;
                 if ((sd ? bchi : bclo) == BC_MOVING) {
@@ -351,6 +673,15 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             n[a] = v;
         }
     }
+    if constexpr (CT != 0) {
+        // per-lane base terms once every pull is in flight
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
+            sgroup<CT>();
+        }
+    }
+    phase_fence<CT>();
     // lagged own-cell force sums sum_a A+^i_a s_a(q, t-1), formed when the
     // previous step produced N'(q, t-1)
     constexpr uint32_t ET = sizeof(T);
@@ -391,7 +722,9 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
         const int a = pair_rep(p), b = opp(a);
         Ln1 += tb(TB::A1(a)) * n[b] + tb(TB::A1(b)) * n[a];
         Ln2 += tb(TB::A2(a)) * n[b] + tb(TB::A2(b)) * n[a];
+        sgroup<CT>();
     }
+    phase_fence<CT>();
     for (int it = 0;; ++it) {
         // ---- force: J F = -1/2 [C + sum_a A+_a (s_a + n_{-a})] + m a_ext ----
         T L1 = Ln1, L2 = Ln2;
@@ -403,6 +736,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             for (int a = 1; a < Q; ++a) {
                 L1 += tb(TB::A1(a)) * s[a];
                 L2 += tb(TB::A2(a)) * s[a];
+                sgroup<CT>();
             }
         }
         JF1 = (T)-0.5 * L1 + ma1;
@@ -437,8 +771,10 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             if (c1 != 0) P11 += tb(TB::X11(p)) * mo;
             if (c2 != 0) P22 += tb(TB::X22(p)) * mo;
             P12 += tb(TB::X12(p)) * mo;
+            sgroup<CT>();
         }
         const T trP = P11 + P22;
+        phase_fence<CT>();
 
         // ---- even part, curvilinear correction and BGK (offset form) ----
         {
@@ -461,7 +797,9 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             const T odd = (T)(w * c1 / T0d) * JF1 + (T)(w * c2 / T0d) * JF2;
             s[a] = omw * n[a] + (omega * feqA + (even + odd));
             s[b] = omw * n[b] + (omega * feqB + (even - odd));
+            sgroup<CT>();
         }
+        phase_fence<CT>();
         if (it >= iters) break;
     }
 
@@ -493,9 +831,10 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
         }
     }
 
+    phase_fence<CT>();
     if constexpr (MOM) {
         const int c = i * n2 + j;
-        const int e = CELL ? c : i;
+        const int e = CT ? c : i;
         double *mo = d->mom;
         const size_t nc = (size_t)d->ncell;
         mo[c] = d->mB64[e] + (double)dm;
@@ -515,6 +854,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
                 Lx1 += tb(TB::A1(a)) * v;
                 Lx2 += tb(TB::A2(a)) * v;
             }
+            sgroup<CT>();
         }
         const __amdgpu_buffer_rsrc_t rlago = make_rsrc(d->lag[pin ^ 1], lag_bytes);
         bstore<T, T>(rlago, jt, rowt, Lx1);
@@ -535,24 +875,24 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
 
 // One tile (row segment of 64 columns per wave) per workgroup.  The tile
 // table holds (instance, first row, first column, lattice).
-template <int Q, typename T, typename S, bool CELL, bool MOM, bool ITER>
+template <int Q, typename T, typename S, int CT, bool MOM, bool ITER>
 __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts, const int4 *__restrict__ tiles,
                                               int par)
 {
-    step_tile<Q, T, S, CELL, MOM, ITER>(insts, tiles[blockIdx.x], par);
+    step_tile<Q, T, S, CT, MOM, ITER>(insts, tiles[blockIdx.x], par);
 }
 
 // D2Q9 and D2Q21 tiles in one launch: the lattice is the tile's fourth field
 // (wave-uniform, so each workgroup runs one of the two bodies).
-template <typename T, typename S, bool CELL, bool MOM, bool ITER>
+template <typename T, typename S, int CT, bool MOM, bool ITER>
 __global__ __launch_bounds__(256) void k_step_mixed(const InstDesc *__restrict__ insts,
                                                     const int4 *__restrict__ tiles, int par)
 {
     const int4 tl = tiles[blockIdx.x];
     if (tl.w == 9)
-        step_tile<9, T, S, CELL, MOM, ITER>(insts, tl, par);
+        step_tile<9, T, S, CT, MOM, ITER>(insts, tl, par);
     else
-        step_tile<21, T, S, CELL, MOM, ITER>(insts, tl, par);
+        step_tile<21, T, S, CT, MOM, ITER>(insts, tl, par);
 }
 
 } // namespace lbm

@@ -30,6 +30,8 @@ struct lbm_grid {
     lbm_grid_desc desc{};
     int q = 0, n1 = 0, n2 = 0, h = 0, pitch = 0, hw = 0, ncell = 0;
     int row = 1, nent = 0;
+    int ct = 0;                   // step tables: 0 per row, 1 per cell, 2 per cell rebuilt from the geometry
+    double *ge = nullptr;         // staged geometry of ct = 2 (GE_* fields)
     int precision = LBM_FP64;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -146,40 +148,58 @@ static unsigned occupancy_lds(int cap, int wpb)
 // kernel dispatch tables -------------------------------------------------------
 typedef void (*StepFn)(const InstDesc *, const int4 *, int);
 
-template <int Q, bool CELL, bool MOM, bool ITER>
+template <int Q, int CT, bool MOM, bool ITER>
 static StepFn step_fn3(int precision)
 {
-    if (precision == LBM_FP64) return k_step<Q, double, double, CELL, MOM, ITER>;
-    if (precision == LBM_FP16) return k_step<Q, float, _Float16, CELL, MOM, ITER>;
-    return k_step<Q, float, float, CELL, MOM, ITER>;
+    if (precision == LBM_FP64) return k_step<Q, double, double, CT, MOM, ITER>;
+    if (precision == LBM_FP16) return k_step<Q, float, _Float16, CT, MOM, ITER>;
+    return k_step<Q, float, float, CT, MOM, ITER>;
 }
 
+// the moments pass reads the stored tables (per-cell tables exist for every
+// per-cell grid)
 template <int Q>
-static StepFn step_fn(int precision, int cell, int mom, int iter)
+static StepFn step_fn(int precision, int ct, int mom, int iter)
 {
-    if (mom) return cell ? step_fn3<Q, true, true, false>(precision) : step_fn3<Q, false, true, false>(precision);
-    if (iter) return cell ? step_fn3<Q, true, false, true>(precision) : step_fn3<Q, false, false, true>(precision);
-    return cell ? step_fn3<Q, true, false, false>(precision) : step_fn3<Q, false, false, false>(precision);
+    if (mom) return ct ? step_fn3<Q, 1, true, false>(precision) : step_fn3<Q, 0, true, false>(precision);
+    if (iter)
+        return ct == 2 ? step_fn3<Q, 2, false, true>(precision)
+                       : (ct ? step_fn3<Q, 1, false, true>(precision) : step_fn3<Q, 0, false, true>(precision));
+    return ct == 2 ? step_fn3<Q, 2, false, false>(precision)
+                   : (ct ? step_fn3<Q, 1, false, false>(precision) : step_fn3<Q, 0, false, false>(precision));
 }
 
-// kernel for a grid or batch group: lattice, storage precision, per-cell
-// tables, moments pass, fixed-point force passes (iterations > 0)
-template <bool CELL, bool ITER>
+// kernel for a grid or batch group: lattice, storage precision, table kind,
+// moments pass, fixed-point force passes (iterations > 0)
+template <int CT, bool ITER>
 static StepFn mixed_fn(int precision)
 {
-    if (precision == LBM_FP64) return k_step_mixed<double, double, CELL, false, ITER>;
-    if (precision == LBM_FP16) return k_step_mixed<float, _Float16, CELL, false, ITER>;
-    return k_step_mixed<float, float, CELL, false, ITER>;
+    if (precision == LBM_FP64) return k_step_mixed<double, double, CT, false, ITER>;
+    if (precision == LBM_FP16) return k_step_mixed<float, _Float16, CT, false, ITER>;
+    return k_step_mixed<float, float, CT, false, ITER>;
 }
 
 // q = 0: a batch group holding both lattices (one fused launch, no moments pass)
-static StepFn pick_step(int q, int precision, int cell, int mom, int iter)
+static StepFn pick_step(int q, int precision, int ct, int mom, int iter)
 {
     if (q == 0) {
-        if (iter) return cell ? mixed_fn<true, true>(precision) : mixed_fn<false, true>(precision);
-        return cell ? mixed_fn<true, false>(precision) : mixed_fn<false, false>(precision);
+        if (iter) return ct == 2 ? mixed_fn<2, true>(precision) : (ct ? mixed_fn<1, true>(precision) : mixed_fn<0, true>(precision));
+        return ct == 2 ? mixed_fn<2, false>(precision) : (ct ? mixed_fn<1, false>(precision) : mixed_fn<0, false>(precision));
     }
-    return q == 9 ? step_fn<9>(precision, cell, mom, iter) : step_fn<21>(precision, cell, mom, iter);
+    return q == 9 ? step_fn<9>(precision, ct, mom, iter) : step_fn<21>(precision, ct, mom, iter);
+}
+
+// dynamic LDS of a step launch: the occupancy reservation, or the staged
+// geometry of ct = 2 if larger (q = 0, both lattices: the D2Q21 tile)
+static unsigned step_lds(int ct, int q, int precision, int cap, int wpb)
+{
+    unsigned b = occupancy_lds(cap, wpb);
+    if (ct == 2) {
+        const unsigned sg = q == 9 ? (precision == LBM_FP64 ? geo_stage_bytes<9, double>(wpb) : geo_stage_bytes<9, float>(wpb))
+                                   : (precision == LBM_FP64 ? geo_stage_bytes<21, double>(wpb) : geo_stage_bytes<21, float>(wpb));
+        if (sg > b) b = sg;
+    }
+    return b;
 }
 
 // tiles of one grid in row-major order: (instance, first row, first column, lattice)
@@ -245,8 +265,8 @@ static int build_tiles(lbm_grid *g)
 
 static int launch_step(lbm_grid *g, int par, int mom)
 {
-    StepFn fn = pick_step(g->q, g->precision, !g->row, mom, g->h_inst.iters > 0);
-    hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), occupancy_lds(g->cap, g->wpb), g->stream, (const InstDesc *)g->d_inst,
+    StepFn fn = pick_step(g->q, g->precision, g->ct, mom, g->h_inst.iters > 0);
+    hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), step_lds(g->ct, g->q, g->precision, g->cap, g->wpb), g->stream, (const InstDesc *)g->d_inst,
                        (const int4 *)g->d_tiles, par);
     HIPCHK(g, hipGetLastError());
     return LBM_OK;
@@ -305,6 +325,8 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     if (D.precision != LBM_FP64 && D.precision != LBM_FP32 && D.precision != LBM_FP16)
         return fail(nullptr, LBM_EINVAL, "unknown precision");
     if (D.iterations < 0 || D.iterations > 16) return fail(nullptr, LBM_EINVAL, "iterations must be in 0..16");
+    if (D.geometry != LBM_GEOM_AUTO && D.geometry != LBM_GEOM_CELL && D.geometry != LBM_GEOM_CELL_TABLE)
+        return fail(nullptr, LBM_EINVAL, "unknown geometry mode");
     if ((int64_t)D.n1 * D.n2 > (int64_t)1 << 30) return fail(nullptr, LBM_EINVAL, "grid too large");
     {   // one population buffer must stay below 2 GiB (32-bit buffer offsets)
         const int64_t pitch = D.n2 >= 64 ? (D.n2 + 63) / 64 * 64 : D.n2;
@@ -399,8 +421,19 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     HIPB(hipMemcpyAsync(hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, st));
     HIPB(hipStreamSynchronize(st));
     if (hflag[1]) return bail(LBM_EINVAL, "the mapping has J <= 0 (or non-finite geometry) in some cell");
-    g->row = (D.geometry == LBM_GEOM_CELL) ? 0 : (hflag[0] ? 0 : 1);
+    g->row = (D.geometry != LBM_GEOM_AUTO) ? 0 : (hflag[0] ? 0 : 1);
+    g->ct = g->row ? 0 : (D.geometry == LBM_GEOM_CELL_TABLE ? 1 : 2);
     g->nent = g->row ? n1 : nc;
+    const int nfe = g->precision == LBM_FP64 ? (int)GE_J : (int)GE_NF;
+    const size_t gfs = (size_t)(n1 + 2 * cm) * (n2 + 2 * cm);
+    if (g->ct == 2) {
+        // geometry the step stages (the tangents are freed below)
+        g->ge = (double *)dalloc(g, gfs * nfe * 8);
+        if (!g->ge) return bail(LBM_ENOMEM, "device allocation failed (geometry)");
+        hipLaunchKernelGGL(k_geo_ext, dim3((n2 + 2 * cm + 127) / 128, n1 + 2 * cm), dim3(128), 0, st, tg, n1, n2, h, cm, nfe,
+                           g->ge);
+        HIPB(hipGetLastError());
+    }
     if (g->row) {
         hipLaunchKernelGGL(k_canon_rows, cell_grid(n1, n2), dim3(128), 0, st, n1, n2, g->Jgeo, g->G3);
         HIPB(hipGetLastError());
@@ -501,6 +534,11 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     I.iters = D.iterations;
     I.ncell = nc;
     I.par0 = 0;
+    I.sbase = ta.base_kind;
+    I.rho0 = D.rho0;
+    I.geo = g->ge;
+    I.gfs = (long long)gfs;
+    I.gw = n2 + 2 * cm;
     I.ut_lo = D.ut_lo;
     I.ut_hi = D.ut_hi;
     I.a1 = D.accel[0];
@@ -525,6 +563,7 @@ int lbm_grid_info_get(const lbm_grid *g, lbm_grid_info *out)
     out->pitch = g->pitch;
     out->precision = g->precision;
     out->row_tables = g->row;
+    out->table_kind = g->ct;
     out->step = g->step;
     out->bytes_per_update = 2.0 * g->q * (double)store_size(g->precision);
     out->device_bytes = g->bytes;
@@ -553,7 +592,7 @@ int lbm_set_occupancy(lbm_grid *g, int32_t waves_per_cu)
 }
 
 namespace {
-// process-wide autotuner cache: (q, precision, cell tables, n1, n2) ->
+// process-wide autotuner cache: (q, precision, table kind, n1, n2) ->
 // (waves per block, waves per CU cap)
 // (shared by every grid of the process, so guarded)
 std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tuned;
@@ -564,7 +603,7 @@ int lbm_autotune(lbm_grid *g, int32_t steps)
 {
     if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
     if (steps < 2) steps = 2;
-    const auto key = std::make_tuple(g->q, g->precision, g->row ? 0 : 1, g->n1, g->n2);
+    const auto key = std::make_tuple(g->q, g->precision, g->ct, g->n1, g->n2);
     {
         std::pair<int, int> hit{0, 0};
         {
@@ -702,8 +741,8 @@ static int capture_graph(lbm_grid *g, int start_par, int steps)
     HIPCHK(g, hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
     int par = start_par;
     for (int s = 0; s < steps; ++s) {
-        StepFn fn = pick_step(g->q, g->precision, !g->row, 0, g->h_inst.iters > 0);
-        hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), occupancy_lds(g->cap, g->wpb), g->stream, (const InstDesc *)g->d_inst,
+        StepFn fn = pick_step(g->q, g->precision, g->ct, 0, g->h_inst.iters > 0);
+        hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), step_lds(g->ct, g->q, g->precision, g->cap, g->wpb), g->stream, (const InstDesc *)g->d_inst,
                            (const int4 *)g->d_tiles, par);
         par ^= 1;
     }
@@ -1122,7 +1161,7 @@ int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_b
         if (g->stream != b->stream && std::find(b->others.begin(), b->others.end(), g->stream) == b->others.end())
             b->others.push_back(g->stream);
         b->grids.push_back(g);
-        groups[std::make_tuple(fuse ? 0 : g->q, g->precision, g->row ? 0 : 1, g->h_inst.iters > 0 ? 1 : 0)].push_back(k);
+        groups[std::make_tuple(fuse ? 0 : g->q, g->precision, g->ct, g->h_inst.iters > 0 ? 1 : 0)].push_back(k);
     }
     for (auto &kv : groups) {
         lbm_batch::Group G;
@@ -1199,7 +1238,7 @@ static int batch_launch(lbm_batch *b, int par)
 {
     for (auto &G : b->groups) {
         StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter);
-        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), occupancy_lds(G.cap, G.wpb), b->stream, (const InstDesc *)G.d_inst,
+        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), step_lds(G.cell, G.q, G.precision, G.cap, G.wpb), b->stream, (const InstDesc *)G.d_inst,
                            (const int4 *)G.d_tiles, par);
     }
     if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "batch step launch failed");
@@ -1282,7 +1321,7 @@ int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *preci
     if (cells) {
         int64_t c = 0;
         for (lbm_grid *g : b->grids)
-            if ((G.q == 0 || g->q == G.q) && g->precision == G.precision && (g->row ? 0 : 1) == G.cell &&
+            if ((G.q == 0 || g->q == G.q) && g->precision == G.precision && g->ct == G.cell &&
                 (g->h_inst.iters > 0 ? 1 : 0) == G.iter)
                 c += g->ncell;
         *cells = c;
@@ -1297,7 +1336,7 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n)
     const auto &G = b->groups[group];
     StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter);
     for (int64_t k = 0; k < n; ++k)
-        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), occupancy_lds(G.cap, G.wpb), b->stream, (const InstDesc *)G.d_inst,
+        hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), step_lds(G.cell, G.q, G.precision, G.cap, G.wpb), b->stream, (const InstDesc *)G.d_inst,
                            (const int4 *)G.d_tiles, (int)((b->step + k) & 1));
     if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "group step launch failed");
     return LBM_OK;

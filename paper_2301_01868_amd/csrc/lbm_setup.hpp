@@ -74,6 +74,34 @@ __global__ void k_geom_cell(const double *__restrict__ tg, int n1, int n2, int h
     }
 }
 
+// Geometry staged by steps that rebuild their table fields (GE_* fields,
+// [field][n1 + 2 cm][n2 + 2 cm]): the tangents of the cells and of cm layers
+// of the mapping's continuation around them, with J = (g_1 x g_2).z and
+// H = J g^ij: H11 = |g_2|^2 / J, H12 = -g_1.g_2 / J, H22 = |g_1|^2 / J.
+__global__ void k_geo_ext(const double *__restrict__ tg, int n1, int n2, int h, int cm, int nf, double *__restrict__ ge)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = blockIdx.y;
+    const int gw = n2 + 2 * cm, gr = n1 + 2 * cm;
+    if (c >= gw || e >= gr) return;
+    const int H2 = n2 + 2 * h;
+    const size_t nh = (size_t)(n1 + 2 * h) * H2;
+    const size_t k = (size_t)(e - cm + h) * H2 + (c - cm + h);
+    const double g1x = tg[k], g1y = tg[nh + k], g2x = tg[2 * nh + k], g2y = tg[3 * nh + k];
+    const size_t fs = (size_t)gr * gw, o = (size_t)e * gw + c;
+    ge[GE_G1X * fs + o] = g1x;
+    ge[GE_G1Y * fs + o] = g1y;
+    ge[GE_G2X * fs + o] = g2x;
+    ge[GE_G2Y * fs + o] = g2y;
+    if (nf > GE_J) {
+        const double J = g1x * g2y - g1y * g2x;
+        ge[GE_J * fs + o] = J;
+        ge[GE_H11 * fs + o] = (g2x * g2x + g2y * g2y) / J;
+        ge[GE_H12 * fs + o] = -(g1x * g2x + g1y * g2y) / J;
+        ge[GE_H22 * fs + o] = (g1x * g1x + g1y * g1y) / J;
+    }
+}
+
 // row invariance: does any rotation-invariant field (J, g^ij, A+) of cell
 // (i, j) differ from cell (i, 0)?  Also flags non-positive J.
 __global__ void k_rowcheck(const double *__restrict__ geo, int n1, int n2, int nf, double tol, int *__restrict__ flag)

@@ -18,7 +18,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, 
 LBM_PERIODIC, LBM_NOSLIP, LBM_MOVING = 0, 1, 2
 LBM_FP64, LBM_FP32, LBM_FP16 = 0, 1, 2
 LBM_BASE_LOCAL_REST, LBM_BASE_W_RHO0, LBM_BASE_NONE = 0, 1, 2
-LBM_GEOM_AUTO, LBM_GEOM_CELL = 0, 1
+LBM_GEOM_AUTO, LBM_GEOM_CELL, LBM_GEOM_CELL_TABLE = 0, 1, 2
 LBM_BATCH_FUSE_LATTICES = 1
 BC = {"periodic": LBM_PERIODIC, "noslip": LBM_NOSLIP, "moving": LBM_MOVING}
 
@@ -61,7 +61,8 @@ class lbm_grid_info(ct.Structure):
     _fields_ = [("q", ct.c_int32), ("n1", ct.c_int32), ("n2", ct.c_int32), ("pitch", ct.c_int32),
                 ("precision", ct.c_int32), ("row_tables", ct.c_int32), ("step", ct.c_int64),
                 ("bytes_per_update", ct.c_double), ("device_bytes", ct.c_size_t),
-                ("waves_per_block", ct.c_int32), ("waves_per_cu_cap", ct.c_int32)]
+                ("waves_per_block", ct.c_int32), ("waves_per_cu_cap", ct.c_int32),
+                ("table_kind", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 _lib = None

@@ -69,7 +69,7 @@ def test_create_rejects_shapes(lib, kw, what):
 
 def test_create_rejects_modes(lib):
     case = _desc_case()
-    for kw in (dict(precision=7), dict(iterations=17), dict(iterations=-1)):
+    for kw in (dict(precision=7), dict(iterations=17), dict(iterations=-1), dict(geometry=3), dict(geometry=-1)):
         with pytest.raises(lbm.LbmError) as e:
             lbm.Grid(case, **kw)
         assert e.value.code == lbm.LBM_EINVAL, kw

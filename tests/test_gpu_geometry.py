@@ -1,0 +1,143 @@
+"""Per-cell metric terms rebuilt in the step from the staged FP64 geometry
+(LBM_GEOM_CELL, the default for mappings whose terms depend on q2), against
+the FP64 oracle and against the stored per-cell tables (LBM_GEOM_CELL_TABLE)
+(needs an MI355X).
+
+The terms are those of Sec. 2: g^ij (Eq. covectors), the Christoffel sums
+A+^i_a = g^i . [e_a(q + c_a) - e_a(q)] (Eqs. gamma, lattice) and, for offset
+storage, the local rest state of the cell and of each pulled source."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import characteristic_speed, initial_velocity, norm_rel, pair, say, to_oracle_state
+from paper_2301_01868_amd import grids as G
+from paper_2301_01868_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    # q2-dependent mappings (per-cell terms by necessity): narrow and wide
+    # (the wide rows take the kernel's unwrapped fast path), both lattices
+    yield "box_wobble_q21_narrow", G.periodic_box(21, 9, 11, dx=1.0, dy=1.1, skew=0.1, wobble=0.25, tau=0.9)
+    yield "box_wobble_q21_wide", G.periodic_box(21, 10, 150, dx=1.0, dy=1.1, skew=0.1, wobble=0.25, tau=0.9)
+    yield "box_wobble_q9_wide", G.periodic_box(9, 12, 140, dx=1.0, dy=1.2, wobble=0.2, tau=0.8)
+    # row-invariant mappings forced onto the per-cell path: walls at rest,
+    # moving walls (specular sources), a ragged last tile, a stretched channel
+    yield "annulus_q21_moving", G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, u_outer=-0.02, tau=0.8)
+    yield "annulus_q21_wide", G.circular_couette(21, 9, 160, 25.0, u_inner=0.05, tau=0.8)
+    yield "channel_q21_ragged", G.planar_couette(21, G.faces_linear(14, 0.35), n2=70, u_wall=0.04, moving="lo",
+                                                  tau=0.7).replace(accel=(0.0, 2e-6))
+    yield "couette_q9", G.workload_planar_couette_q9()
+
+
+CASES = list(_cases())
+
+
+@pytest.mark.parametrize("name,case", CASES, ids=[c[0] for c in CASES])
+def test_rebuilt_geometry_fp64_matches_oracle(name, case):
+    g, o = pair(case, geometry=lbm.LBM_GEOM_CELL)
+    assert g.info.table_kind == 2 and not g.info.row_tables
+    g.step(300)
+    o.step(300)
+    P, _ = g.get_state()
+    err = norm_rel(to_oracle_state(P), o.get_state())
+    m, U, Ut = g.moments()
+    mo, Uo, Uto = o.moments()
+    say(name, "fp64 rebuilt geometry: state rel err %.2e" % err)
+    assert err <= 1e-12
+    assert np.abs(Ut - Uto).max() <= 1e-12 * max(np.abs(Uto).max(), 1e-3)
+
+
+@pytest.mark.parametrize("name,case", CASES, ids=[c[0] for c in CASES])
+def test_rebuilt_geometry_fp32_within_tolerance(name, case):
+    """FP32 offsets from the local rest state, with the rest state of every
+    pulled source evaluated in FP64 from the staged geometry: velocity within
+    1e-5 of the characteristic speed of the FP64 oracle."""
+    g, o = pair(case, precision=lbm.LBM_FP32, geometry=lbm.LBM_GEOM_CELL)
+    g.step(300)
+    o.step(300)
+    m, U, Ut = g.moments()
+    mo, Uo, Uto = o.moments()
+    geo = o.geometry()
+    u = Ut[:, :1] * geo["g1"] + Ut[:, 1:] * geo["g2"]
+    uo = Uto[:, :1] * geo["g1"] + Uto[:, 1:] * geo["g2"]
+    Uc = characteristic_speed(case, uo)
+    err = np.abs(u - uo).max() / Uc
+    say(name, "fp32 rebuilt geometry: velocity err / U %.2e" % err)
+    assert err <= 1e-5
+    assert norm_rel(m, mo) <= 1e-6
+
+
+@pytest.mark.parametrize("base", [lbm.LBM_BASE_LOCAL_REST, lbm.LBM_BASE_W_RHO0], ids=["local_rest", "w_rho0"])
+@pytest.mark.parametrize("prec", [lbm.LBM_FP64, lbm.LBM_FP32, lbm.LBM_FP16], ids=["fp64", "fp32", "fp16"])
+def test_rebuilt_geometry_equals_stored_tables(prec, base):
+    """On a larger wobbled box (several row tiles and column blocks, a ragged
+    last block), rebuilt and stored per-cell terms give the same trajectory to
+    the rounding of the compute type."""
+    case = G.periodic_box(21, 40, 300, dx=1.0, dy=1.1, skew=0.1, wobble=0.25, tau=0.9)
+    u0 = initial_velocity(case)
+    out = []
+    for geom in (lbm.LBM_GEOM_CELL, lbm.LBM_GEOM_CELL_TABLE):
+        g = lbm.Grid(case, precision=prec, offset_base=base, geometry=geom)
+        assert g.info.table_kind == (2 if geom == lbm.LBM_GEOM_CELL else 1)
+        g.init(u0)
+        g.step(200)
+        out.append((g.get_state()[0], g.moments()[2]))
+        g.close()
+    (Pa, Uta), (Pb, Utb) = out
+    d_state = norm_rel(Pa, Pb)
+    d_u = np.abs(Uta - Utb).max() / np.abs(Utb).max()
+    say("prec", prec, "base", base, "rebuilt vs stored: state %.2e, Ut %.2e" % (d_state, d_u))
+    # FP16 stores an 11-bit mantissa: two paths whose FP32 arithmetic rounds
+    # differently part at the level of FP16's own error against the oracle
+    # (stated at up to 2e-2 of the characteristic speed in the parity tests)
+    tol = {lbm.LBM_FP64: 1e-13, lbm.LBM_FP32: 2e-6, lbm.LBM_FP16: 1e-2}[prec]
+    assert d_u <= tol
+
+
+def test_table_kind_selection():
+    wob = G.periodic_box(21, 9, 11, dx=1.0, dy=1.1, skew=0.1, wobble=0.25, tau=0.9)
+    ann = G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, tau=0.8)
+    assert lbm.Grid(wob).info.table_kind == 2
+    assert lbm.Grid(ann).info.table_kind == 0
+    assert lbm.Grid(ann, geometry=lbm.LBM_GEOM_CELL).info.table_kind == 2
+    assert lbm.Grid(ann, geometry=lbm.LBM_GEOM_CELL_TABLE).info.table_kind == 1
+    assert lbm.Grid(wob, geometry=lbm.LBM_GEOM_CELL_TABLE).info.table_kind == 1
+
+
+@pytest.mark.parametrize("fuse", [0, lbm.LBM_BATCH_FUSE_LATTICES], ids=["groups", "fused"])
+def test_rebuilt_geometry_in_batches(fuse):
+    """Grids with rebuilt per-cell terms form their own launch group (or share
+    the fused launch) and end exactly as they do alone."""
+    cases = [G.periodic_box(21, 10, 150, dx=1.0, dy=1.1, skew=0.1, wobble=0.25, tau=0.9),
+             G.periodic_box(9, 12, 140, dx=1.0, dy=1.2, wobble=0.2, tau=0.8),
+             G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, tau=0.8)]
+    for prec in (lbm.LBM_FP64, lbm.LBM_FP32):
+        alone = [lbm.Grid(c, precision=prec) for c in cases]
+        batched = [lbm.Grid(c, precision=prec) for c in cases]
+        for g, c in zip(alone + batched, cases + cases):
+            g.init(initial_velocity(c))
+        for g in alone:
+            g.step(45)
+        b = lbm.lbm_batch_create_ex([g.h for g in batched], fuse)
+        groups = lbm.lbm_batch_groups(b)
+        say("groups", groups)
+        lbm.lbm_batch_step(b, 45)
+        lbm.lbm_batch_destroy(b)
+        for ga, gb in zip(alone, batched):
+            assert np.array_equal(ga.get_state()[0], gb.get_state()[0])
+
+
+def test_rebuilt_geometry_iterated_force():
+    """Fixed-point passes of the force relation (iterations > 0) read the
+    rebuilt Christoffel sums in every pass."""
+    case = G.periodic_box(21, 10, 150, dx=1.0, dy=1.1, skew=0.1, wobble=0.25, tau=0.9)
+    g, o = pair(case, iterations=2, geometry=lbm.LBM_GEOM_CELL)
+    g.step(100)
+    o.step(100)
+    P, _ = g.get_state()
+    err = norm_rel(to_oracle_state(P), o.get_state())
+    say("iterated force, rebuilt geometry: state rel err %.2e" % err)
+    assert err <= 1e-12
