@@ -68,6 +68,10 @@ def workloads():
         "planar_couette_q9_32x16": lambda: [G.workload_planar_couette_q9()],
         # kernel-scaling probe (not one of the stated workloads): the same annulus family at 16x the cells
         "annulus_couette_1024x4096": lambda: [G.workload_annulus_couette(1024, 4096, tau=0.8)],
+        # general-mapping probe: a sheared, wobbled doubly periodic box whose metric terms depend on
+        # q2, so the step rebuilds them per cell from the staged geometry
+        "wobbled_box_q21_1024x1024": lambda: [G.periodic_box(21, 1024, 1024, dx=1.0, dy=1.1, skew=0.1, wobble=0.25,
+                                                             tau=0.9)],
     }
 
 
@@ -153,11 +157,12 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
     # dominant kernel: the D2Q21 step (algorithmic bytes 2 Q sizeof(population) per cell update)
     s_bytes = {lbm.LBM_FP64: 8, lbm.LBM_FP32: 4, lbm.LBM_FP16: 2}[prec]
     sname = {8: "f64", 4: "f32", 2: "f16"}[s_bytes]
+    kind = {0: "row", 1: "cell tables", 2: "cell geometry"}[grids[0].info.table_kind]
     if batch is None:
         q = cases[0].q
         kcells = cells
         avg_ms = ms / steps
-        kname = "k_step<%d,%s,row>" % (q, sname)
+        kname = "k_step<%d,%s,%s>" % (q, sname, kind)
     else:
         groups = lbm.lbm_batch_groups(batch)
         gi = max(range(len(groups)), key=lambda k: (groups[k][0] == 21, groups[k][2]))
@@ -170,7 +175,7 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
         ev1.record(stream)
         torch.cuda.synchronize()
         avg_ms = ev0.elapsed_time(ev1) / reps
-        kname = "k_step<%d,%s,row> (batch group of %d cells)" % (q, sname, kcells)
+        kname = "k_step<%d,%s,%s> (batch group of %d cells)" % (q, sname, kind, kcells)
     alg_bytes = 2 * q * s_bytes * kcells
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     traffic = recorded_traffic(workload, sname, kcells) if (workload and iterations == 0) else None

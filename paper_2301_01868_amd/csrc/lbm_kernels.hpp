@@ -265,11 +265,24 @@ __host__ __device__ constexpr int geo_stage_fields()
 {
     return sizeof(T) == 4 ? GE_NF : GE_J;
 }
-// LDS bytes of one workgroup's staged geometry (wpb rows of 64 cells)
-template <int Q, typename T>
-__host__ __device__ constexpr unsigned geo_stage_bytes(int wpb)
+// Staged tile of a workgroup of up to 4 rows of 64 cells: [field][4 + 2 c_max]
+// [64 + 2 c_max] whatever the workgroup's row count, so that every offset in
+// it is a compile-time constant
+template <int Q>
+__host__ __device__ constexpr int geo_tile_cols()
 {
-    return (unsigned)(geo_stage_fields<T>() * (wpb + 2 * cmax<Q>()) * (64 + 2 * cmax<Q>()) * sizeof(double));
+    return 64 + 2 * cmax<Q>();
+}
+template <int Q>
+__host__ __device__ constexpr int geo_tile_field()
+{
+    return (4 + 2 * cmax<Q>()) * geo_tile_cols<Q>();
+}
+// LDS bytes of one workgroup's staged geometry
+template <int Q, typename T>
+__host__ __device__ constexpr unsigned geo_stage_bytes()
+{
+    return (unsigned)(geo_stage_fields<T>() * geo_tile_field<Q>() * sizeof(double));
 }
 
 // rho0-free local rest state J phi_rest of direction a; s = -1 reflects the
@@ -285,15 +298,14 @@ __device__ inline double jrest(int a, double J, double h11, double h12, double h
 }
 
 // Copy the geometry of the workgroup's rows tl.y .. tl.y + wpb - 1 and columns
-// tl.z .. tl.z + 63, with c_max layers around them, into LDS
-// [field][wpb + 2 c_max][64 + 2 c_max].  Entries outside the stored range
-// (rows or columns past the grid's continuation) are zero and never read by a
-// cell inside the grid.
+// tl.z .. tl.z + 63, with c_max layers around them, into the LDS tile.
+// Entries outside the stored range (rows or columns past the grid's
+// continuation) are zero and never read by a cell inside the grid.
 template <int Q, typename T>
 __device__ __forceinline__ const double *stage_geometry(const InstDesc *__restrict__ d, const int4 tl, int wave)
 {
     extern __shared__ double geo_lds[];
-    constexpr int CM = cmax<Q>(), TC = 64 + 2 * CM;
+    constexpr int CM = cmax<Q>(), TC = geo_tile_cols<Q>(), FS = geo_tile_field<Q>();
     constexpr int NF = geo_stage_fields<T>();
     const int nw = (int)(blockDim.x >> 6), TR = nw + 2 * CM;
     const int lane = (int)(threadIdx.x & 63);
@@ -322,7 +334,10 @@ __device__ __forceinline__ const double *stage_geometry(const InstDesc *__restri
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int cc = lane + 64 * h;
-                if (row < NF * TR && cc < TC) geo_lds[row * TC + cc] = v[u][h];
+                if (row < NF * TR && cc < TC) {
+                    const int f = row / TR, rr = row - f * TR;
+                    geo_lds[f * FS + rr * TC + cc] = v[u][h];
+                }
             }
         }
     }
@@ -338,13 +353,14 @@ struct GeoTab {
     // offsets: compute relative to the local rest state (FP32 compute), else
     // with the particle numbers themselves (FP64)
     static constexpr bool CB = sizeof(T) == 4;
+    static constexpr int TC = geo_tile_cols<Q>(), FS = geo_tile_field<Q>();
     const double *L;   // staged geometry
-    int o, tc, fs;     // own cell in a staged field, row stride, field stride
+    int o;             // own cell in a staged field
     int i, n1, per1, bclo, bchi, sbase;
     double g1x, g1y, g2x, g2y, J, h11, h12, h22, rho0;
     T u1x, u1y, u2x, u2y, G11, G12, G22, mb, c1s, c2s, kpi;
 
-    __device__ __forceinline__ double ld(int f, int dr, int dc) const { return L[f * fs + o + dr * tc + dc]; }
+    __device__ __forceinline__ double ld(int f, int dr, int dc) const { return L[o + (f * FS + dr * TC + dc)]; }
 
     // e_a(q + c_a) - e_a(q)
     __device__ __forceinline__ void dA(int a, double &dx, double &dy) const
@@ -377,13 +393,11 @@ struct GeoTab {
         }
     }
 
-    __device__ __forceinline__ void setup(const InstDesc *__restrict__ d, const double *lds, int nw, int wave, int lane,
-                                          int row, int col)
+    __device__ __forceinline__ void setup(const InstDesc *__restrict__ d, const double *lds, int wave, int lane, int row,
+                                          int col)
     {
         L = lds;
-        tc = 64 + 2 * CM;
-        fs = (nw + 2 * CM) * tc;
-        o = (wave + CM) * tc + lane + CM;
+        o = (wave + CM) * TC + lane + CM;
         i = row;
         n1 = d->n1;
         per1 = d->periodic1;
@@ -584,7 +598,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
 
     typename TabSel<Q, T, CT>::type tb;
     if constexpr (CT == 2) {
-        tb.setup(d, geo_lds, (int)(blockDim.x >> 6), wave, j - j0, i, j);
+        tb.setup(d, geo_lds, wave, j - j0, i, j);
     } else if constexpr (CT == 1) {
         tb.p = (const T *)d->tab + (size_t)i * n2 + j;
         tb.s = d->ncell;

@@ -195,8 +195,8 @@ static unsigned step_lds(int ct, int q, int precision, int cap, int wpb)
 {
     unsigned b = occupancy_lds(cap, wpb);
     if (ct == 2) {
-        const unsigned sg = q == 9 ? (precision == LBM_FP64 ? geo_stage_bytes<9, double>(wpb) : geo_stage_bytes<9, float>(wpb))
-                                   : (precision == LBM_FP64 ? geo_stage_bytes<21, double>(wpb) : geo_stage_bytes<21, float>(wpb));
+        const unsigned sg = q == 9 ? (precision == LBM_FP64 ? geo_stage_bytes<9, double>() : geo_stage_bytes<9, float>())
+                                   : (precision == LBM_FP64 ? geo_stage_bytes<21, double>() : geo_stage_bytes<21, float>());
         if (sg > b) b = sg;
     }
     return b;

@@ -77,3 +77,25 @@ def pair(case, precision=lbm.LBM_FP64, iterations=0, **kw):
     g.init(u0)
     o.init(case.rho0, u0)
     return g, o
+
+
+def one_step_sampled(g, case, nsample=1500, seed=0):
+    """One GPU step from the grid's current state against the oracle's step of
+    the same state on sampled cells (every wall-adjacent row plus random
+    interior cells); max relative difference."""
+    P0, side0 = g.get_state()
+    o = oracle.OracleGrid(case)
+    o.set_state(to_oracle_state(P0))
+    m_s, u_s = side_to_oracle(side0, case.n1, case.n2)
+    o.set_side(np.nan_to_num(m_s), np.nan_to_num(u_s))
+    rng = np.random.default_rng(seed)
+    # every wall-adjacent row plus random interior cells
+    rows = list(range(min(4, case.n1))) + list(range(max(0, case.n1 - 4), case.n1))
+    cells = [r * case.n2 + int(rng.integers(case.n2)) for r in rows]
+    cells += list(rng.choice(case.ncell, nsample, replace=False))
+    cells = np.array(sorted(set(cells)), dtype=np.int32)
+    ref = o.step_cells(cells)
+    g.step(1)
+    P1, _ = g.get_state()
+    got = to_oracle_state(P1)[cells]
+    return np.abs(got - ref).max() / np.abs(ref).max()

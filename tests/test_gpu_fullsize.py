@@ -8,30 +8,11 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import norm_rel, say, side_to_oracle, to_oracle_state
+from gpu_util import one_step_sampled as _one_step_sampled, say
 from paper_2301_01868_amd import grids as G
 from paper_2301_01868_amd import lbm
 
 pytestmark = pytest.mark.gpu
-
-
-def _one_step_sampled(g, case, nsample=1500, seed=0):
-    P0, side0 = g.get_state()
-    o = oracle.OracleGrid(case)
-    o.set_state(to_oracle_state(P0))
-    m_s, u_s = side_to_oracle(side0, case.n1, case.n2)
-    o.set_side(np.nan_to_num(m_s), np.nan_to_num(u_s))
-    rng = np.random.default_rng(seed)
-    # every wall-adjacent row plus random interior cells
-    rows = list(range(min(4, case.n1))) + list(range(max(0, case.n1 - 4), case.n1))
-    cells = [r * case.n2 + int(rng.integers(case.n2)) for r in rows]
-    cells += list(rng.choice(case.ncell, nsample, replace=False))
-    cells = np.array(sorted(set(cells)), dtype=np.int32)
-    ref = o.step_cells(cells)
-    g.step(1)
-    P1, _ = g.get_state()
-    got = to_oracle_state(P1)[cells]
-    return np.abs(got - ref).max() / np.abs(ref).max()
 
 
 @pytest.mark.parametrize("prec,steps,tol1,tolu", [(lbm.LBM_FP32, 2000, 3e-6, 1e-5), (lbm.LBM_FP64, 600, 1e-13, 1e-12),

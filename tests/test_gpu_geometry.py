@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import characteristic_speed, initial_velocity, norm_rel, pair, say, to_oracle_state
+from gpu_util import characteristic_speed, initial_velocity, norm_rel, one_step_sampled, pair, say, to_oracle_state
 from paper_2301_01868_amd import grids as G
 from paper_2301_01868_amd import lbm
 
@@ -141,3 +141,54 @@ def test_rebuilt_geometry_iterated_force():
     err = norm_rel(to_oracle_state(P), o.get_state())
     say("iterated force, rebuilt geometry: state rel err %.2e" % err)
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("prec,steps,tolu,tol1", [(lbm.LBM_FP64, 600, 1e-11, 1e-13), (lbm.LBM_FP32, 2000, 1e-5, 3e-6)],
+                         ids=["fp64", "fp32"])
+def test_rebuilt_geometry_full_size_annulus(prec, steps, tolu, tol1):
+    """A 128 x 1024 annulus (R2 = 2 R1, cells of aspect 0.79 to 1.57) forced
+    onto the per-cell path: every column is rebuilt from its own staged
+    geometry (rotated copies of the same row, equal only to rounding), and the
+    state still follows the oracle's exact theta-reduction.  In FP64 the
+    columns' Christoffel sums, differences of neighbouring tangents, differ
+    from the reduction's single column by rounding amplified by the 1/(r dtheta)
+    of a difference (~1e-13 relative), hence 1e-11 of U against the reduction;
+    the step's own arithmetic is then checked cell by cell against the
+    oracle's step of the same state on the full grid.  (The 256 x 1024
+    annulus, whose outer cells reach aspect 3.1, is unstable to the
+    non-axisymmetric perturbations such rounding seeds, on the oracle as on
+    the GPU; only its exactly theta-invariant form is stable.)"""
+    case = G.circular_couette(21, 128, 1024, 128.0, u_inner=0.05, tau=0.8)
+    g = lbm.Grid(case, precision=prec, geometry=lbm.LBM_GEOM_CELL)
+    assert g.info.table_kind == 2
+    g.init()
+    g.step(steps)
+    red = oracle.OracleGrid(G.circular_couette(21, 128, 1024, 128.0, u_inner=0.05, tau=0.8, n2=1))
+    red.init(1.0)
+    red.step(steps)
+    m, U, Ut = g.moments()
+    mo, Uo, Uto = red.moments()
+    sdt = np.sin(case.meta["dtheta"])
+    r_c = case.meta["centres"]
+    uth = Ut.reshape(128, 1024, 2)[:, :, 1] * r_c[:, None] * sdt
+    uth_o = Uto[:, 1] * r_c * sdt
+    err = np.abs(uth - uth_o[:, None]).max()
+    say("annulus 128x1024 rebuilt geometry prec", prec, "u_theta err / U %.2e" % (err / 0.05))
+    assert err <= tolu * 0.05
+    # the per-cell arithmetic itself, on the full grid's own geometry
+    e1 = one_step_sampled(g, case)
+    say("one-step sampled rel err %.2e" % e1)
+    assert e1 <= tol1
+
+
+def test_rebuilt_geometry_noflow_volume():
+    """The "no flow" adjustment on the per-cell path gives the per-row path's
+    volume J' (Sec. 3.1)."""
+    case = G.circular_couette(21, 10, 80, 10.0, u_inner=0.05, tau=1.0)
+    vols = []
+    for geom in (lbm.LBM_GEOM_AUTO, lbm.LBM_GEOM_CELL):
+        g = lbm.Grid(case, geometry=geom)
+        steps = g.noflow_adjust(tol=1e-12, check_every=500)
+        vols.append((steps, g.get_volume()))
+    assert vols[0][0] == vols[1][0]
+    assert norm_rel(vols[1][1], vols[0][1]) <= 1e-12
