@@ -129,7 +129,8 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
         if wpb:
             g.set_launch(wpb)
         else:
-            g.autotune(10)
+            # enough steps per trial shape to time it above the noise (about 4e8 lattice updates)
+            g.autotune(max(10, min(200, int(4e8 // max(c.ncell, 1)))))
         g.init()
         grids.append(g)
     cells = sum(c.ncell for c in cases)
