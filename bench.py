@@ -72,6 +72,10 @@ def workloads():
         # q2, so the step rebuilds them per cell from the staged geometry
         "wobbled_box_q21_1024x1024": lambda: [G.periodic_box(21, 1024, 1024, dx=1.0, dy=1.1, skew=0.1, wobble=0.25,
                                                              tau=0.9)],
+        # the same box without the wobble: constant metric terms, so per-row tables (or, with
+        # --geometry cell / cell_table, the per-cell paths on identical geometry)
+        "sheared_box_q21_1024x1024": lambda: [G.periodic_box(21, 1024, 1024, dx=1.0, dy=1.1, skew=0.1, wobble=0.0,
+                                                             tau=0.9)],
     }
 
 
@@ -114,7 +118,7 @@ def cpu_baseline(case, target_s=15.0, single_s=6.0):
             "single_core_value": case.ncell * k1 / dt1 / 1e6, "cpu_model": cpu_model()}
 
 
-def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbatched=False, iterations=0):
+def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbatched=False, iterations=0, geometry=0):
     """Create, initialise and time `steps` steps of the workload; returns a dict.
     With unbatched=True a batched workload is also timed one grid at a time
     (each grid stepped alone through its own graphs, one after the other).
@@ -125,7 +129,7 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
 
     grids = []
     for c in cases:
-        g = lbm.Grid(c, precision=prec, stream=ct_stream(stream), iterations=iterations)
+        g = lbm.Grid(c, precision=prec, stream=ct_stream(stream), iterations=iterations, geometry=geometry)
         if wpb:
             g.set_launch(wpb)
         else:
@@ -179,7 +183,7 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
         kname = "k_step<%d,%s,%s> (batch group of %d cells)" % (q, sname, kind, kcells)
     alg_bytes = 2 * q * s_bytes * kcells
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = recorded_traffic(workload, sname, kcells) if (workload and iterations == 0) else None
+    traffic = recorded_traffic(workload, sname, kcells) if (workload and iterations == 0 and geometry == 0) else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
             "bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_ms * 1e3, 3)}
@@ -222,6 +226,9 @@ def main():
     ap.add_argument("--no-sequential", action="store_true",
                     help="serving: skip the sequential FP64 replay (long traces)")
     ap.add_argument("--duration", type=float, default=20.0)
+    ap.add_argument("--geometry", default="auto", choices=["auto", "cell", "cell_table"],
+                    help="metric terms per row when they allow it (auto), per cell rebuilt from the geometry in "
+                         "the step (cell), or per cell from stored tables (cell_table)")
     ap.add_argument("--iterations", type=int, default=0,
                     help="fixed-point passes of the force relation (0: the paper's lagged force)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -284,15 +291,17 @@ def main():
     cases = workloads()[args.workload]()
     stream = torch.cuda.Stream()
     it = args.iterations
+    geom = {"auto": lbm.LBM_GEOM_AUTO, "cell": lbm.LBM_GEOM_CELL, "cell_table": lbm.LBM_GEOM_CELL_TABLE}[args.geometry]
     r32 = measure(cases, lbm.LBM_FP32, args.steps, args.warmup, args.wpb, stream, args.workload, unbatched=True,
-                  iterations=it)
+                  iterations=it, geometry=geom)
     r64 = None
     if not args.no_fp64:
         r64 = measure(cases, lbm.LBM_FP64, max(2, args.steps // 2), max(2, args.warmup // 2), args.wpb, stream,
-                      args.workload, iterations=it)
+                      args.workload, iterations=it, geometry=geom)
     r16 = None
     if not args.no_fp16:
-        r16 = measure(cases, lbm.LBM_FP16, args.steps, args.warmup, args.wpb, stream, args.workload, iterations=it)
+        r16 = measure(cases, lbm.LBM_FP16, args.steps, args.warmup, args.wpb, stream, args.workload, iterations=it,
+                      geometry=geom)
 
     cpu = None
     if not args.no_cpu:
@@ -314,7 +323,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": r32["cells"], "q21_cells": r32["q21_cells"],
                    "grids": len(cases), "precision": "fp32 populations (offsets from the local rest state)",
-                   "force": "lagged" if it == 0 else "%d fixed-point passes" % it,
+                   "force": "lagged" if it == 0 else "%d fixed-point passes" % it, "geometry": args.geometry,
                    "bad_cells_after": r32["bad_cells"], "unstable_instances": r32["unstable"]},
         "roofline": r32["roofline"],
         "cpu_baseline": cpu,
