@@ -225,6 +225,38 @@ def poiseuille_g2_for_peak(Nr, Ntheta, M, nu, u_peak):
 # ---------------------------------------------------------------------------
 # the workloads
 # ---------------------------------------------------------------------------
+def eccentric_annulus(q, Nr, Ntheta, M, ecc, u_inner=0.05, tau=1.0, n2=None, halo=None, **kw):
+    """Journal bearing: the gap between an inner circle of radius R1 = M centred
+    at (ecc, 0), sliding at u_inner, and an outer circle of radius R2 = M + Nr
+    centred at the origin, at rest.  Each theta line blends the two walls,
+    x(s, theta) = (1 - s) (c + R1 e(theta)) + s R2 e(theta) with
+    e = (cos theta, sin theta), c = (ecc, 0) and s = (i - 1/2) / Nr, so the
+    mean wall-normal step is 1.  For ecc != 0 the grid is not orthogonal
+    (g_1 . g_2 = -ecc sin(theta) |g_2| / Nr) and its metric terms depend on q2.
+    The ghost rows continue the blend beyond s = 0 and 1, which places them at
+    the mirror image of the interior rows through the wall point of the same
+    theta index."""
+    h = halo if halo is not None else CMAX[q] + 1
+    n2 = Ntheta if n2 is None else n2
+    R1, R2 = float(M), float(M + Nr)
+    if not 0.0 <= ecc < 0.5 * Nr:
+        raise ValueError("eccentricity must leave the gap at least half its mean width")
+    sc = (np.arange(Nr, dtype=np.float64) + 0.5) / Nr
+    s = _reflect_rows(sc, Nr, h, 0.0, 1.0)
+    dth = 2.0 * np.pi / Ntheta
+    th = (np.arange(-h, n2 + h, dtype=np.float64) + 0.5) * dth
+    cs, sn = np.cos(th)[None, :], np.sin(th)[None, :]
+    S = s[:, None]
+    X = (1.0 - S) * (ecc + R1 * cs) + S * R2 * cs
+    Y = (1.0 - S) * R1 * sn + S * R2 * sn
+    c = Case(q=q, n1=Nr, n2=n2, halo=h, X=np.ascontiguousarray(X), Y=np.ascontiguousarray(Y),
+             bc_lo="moving" if u_inner != 0.0 else "noslip", bc_hi="noslip", ut_lo=wall_ut_polar(R1, dth, u_inner),
+             tau=tau, **kw)
+    c.meta.update(family="eccentric", problem="journal_bearing", Nr=Nr, Ntheta=Ntheta, M=M, R1=R1, R2=R2, ecc=ecc,
+                  dtheta=dth, u_inner=u_inner)
+    return c
+
+
 def workload_planar_couette_q9():
     """Planar Couette, D2Q9, 16 wall-normal x 32 periodic cells with the
     periodic step twice the wall-normal step (dx = 2 dy), one wall at rest,

@@ -23,6 +23,10 @@ def _cases():
     yield "box_wobble_q21_narrow", G.periodic_box(21, 9, 11, dx=1.0, dy=1.1, skew=0.1, wobble=0.25, tau=0.9)
     yield "box_wobble_q21_wide", G.periodic_box(21, 10, 150, dx=1.0, dy=1.1, skew=0.1, wobble=0.25, tau=0.9)
     yield "box_wobble_q9_wide", G.periodic_box(9, 12, 140, dx=1.0, dy=1.2, wobble=0.2, tau=0.8)
+    # non-orthogonal and wall-bounded: the journal bearing (eccentric annulus),
+    # inner wall sliding
+    yield "eccentric_q21", G.eccentric_annulus(21, 16, 150, 16.0, 1.0, tau=1.0)
+    yield "eccentric_q9", G.eccentric_annulus(9, 16, 150, 16.0, 2.0, tau=1.0)
     # row-invariant mappings forced onto the per-cell path: walls at rest,
     # moving walls (specular sources), a ragged last tile, a stretched channel
     yield "annulus_q21_moving", G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, u_outer=-0.02, tau=0.8)

@@ -21,6 +21,7 @@ def _cases():
     yield "box_q9", G.periodic_box(9, 7, 66, dx=1.0, dy=1.4, tau=0.6)
     yield "annulus_poiseuille_q9", G.circular_poiseuille(9, 6, 80, 10.0, g2=1e-4, tau=0.7)
     yield "narrow_q21", G.planar_couette(21, G.faces_uniform(3), n2=5, u_wall=0.03, tau=1.0)
+    yield "eccentric_q21_nonorthogonal", G.eccentric_annulus(21, 10, 90, 12.0, 1.0, tau=1.0)
 
 
 CASES = list(_cases())

@@ -75,3 +75,33 @@ def test_aminus_is_minus_aplus_of_opposite(q):
     opp = [int(np.where((cl == -cl[a]).all(1))[0][0]) for a in range(q)]
     assert np.allclose(geo["Aminus"], -geo["Aplus"][:, opp], atol=1e-14)
     assert np.abs(geo["G"][:, 1]).max() > 0.01      # the skewed grid is non-orthogonal
+
+
+@pytest.mark.parametrize("q", [9, 21])
+def test_eccentric_annulus_closed_forms(q):
+    """A non-orthogonal mapping (the journal-bearing blend of two circles):
+    x(s, theta) = (1 - s) c + r(s) e(theta), r(s) = (1 - s) R1 + s R2.  The
+    central differences are exact in s and give, per cell,
+      g_1 = ((R2 - R1) e - c) / Nr,   g_2 = r sin(dtheta) e_perp,
+      J = r sin(dtheta) (1 - (ecc / Nr) cos(theta)),
+      g_1 . g_2 = ecc sin(theta) r sin(dtheta) / Nr,  g^12 = -g_1 . g_2 / J^2."""
+    Nr, Nt, M, ecc = 10, 40, 8.0, 3.0
+    c = G.eccentric_annulus(q, Nr, Nt, M, ecc)
+    o = oracle.OracleGrid(c)
+    geo = o.geometry()
+    dth = 2 * math.pi / Nt
+    s = (np.arange(Nr) + 0.5) / Nr
+    r = np.repeat((1 - s) * M + s * (M + Nr), Nt)
+    th = np.tile((np.arange(Nt) + 0.5) * dth, Nr)
+    e = np.stack([np.cos(th), np.sin(th)], 1)
+    ep = np.stack([-np.sin(th), np.cos(th)], 1)
+    g1 = (Nr * e - np.array([ecc, 0.0])) / Nr
+    g2 = (r * math.sin(dth))[:, None] * ep
+    J = r * math.sin(dth) * (1 - ecc / Nr * np.cos(th))
+    g12 = ecc * np.sin(th) * r * math.sin(dth) / Nr
+    assert np.allclose(geo["g1"], g1, rtol=0, atol=1e-13)
+    assert np.allclose(geo["g2"], g2, rtol=0, atol=1e-12)
+    assert np.allclose(geo["J"], J, rtol=1e-12, atol=0)
+    assert np.allclose((geo["g1"] * geo["g2"]).sum(1), g12, rtol=0, atol=1e-12)
+    assert np.allclose(geo["G"][:, 1], -g12 / J ** 2, rtol=1e-10, atol=1e-14)
+    assert np.abs(geo["G"][:, 1]).max() > 0.05      # genuinely non-orthogonal
