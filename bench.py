@@ -235,7 +235,7 @@ def main():
                     help="only run the library's plain copy kernel on MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (each box has one MI355X); "
+        print("bench.py measures one GPU: the library has no multi-GPU path (one process drives one MI355X); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
