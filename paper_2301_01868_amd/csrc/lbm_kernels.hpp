@@ -243,11 +243,13 @@ struct TabView {
 
 // ---------------------------------------------------------------------------
 // Per-cell table fields rebuilt from the geometry (general mappings).  A grid
-// whose metric terms depend on q2 can step without a stored per-cell table:
-// the workgroup stages the FP64 tangents g_1, g_2 of its cells and of c_max
-// layers around them (and, for offset storage, J and H = J g^ij) into LDS,
-// and every field of Tab<Q> is evaluated where the step uses it, from the
-// cell's own geometry and that of q + c_a, q - c_a or the pulled source:
+// whose metric terms depend on q2 can step without streaming a stored table
+// of every term: the workgroup stages the FP64 tangents g_1, g_2 of its cells
+// and of c_max layers around them (and, for offset storage, J and H = J g^ij)
+// into LDS, and the fields of Tab<Q> are evaluated where the step uses them,
+// from the cell's own geometry and that of q + c_a, q - c_a or the pulled
+// source (only the base's share of the force sum, two values per cell, is
+// read from the grid's per-cell table):
 //   A+^i_a(q) = g^i(q) . [e_a(q + c_a) - e_a(q)],  e_a = c^1_a g_1 + c^2_a g_2   (Eq. gamma)
 //   S^i_a = A+^i_a + A+^i_{-a} = g^i(q) . [e_a(q + c_a) - e_a(q - c_a)]
 // The differences of neighbouring tangents are taken in FP64, so the
