@@ -132,9 +132,12 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
         g = lbm.Grid(c, precision=prec, stream=ct_stream(stream), iterations=iterations, geometry=geometry)
         if wpb:
             g.set_launch(wpb)
-        else:
-            # enough steps per trial shape to time it above the noise (about 4e8 lattice updates)
+        elif len(cases) == 1:
+            # a single grid: enough steps per trial shape to time it above the noise
+            # (about 4e8 lattice updates)
             g.autotune(max(10, min(200, int(4e8 // max(c.ncell, 1)))))
+        else:
+            g.autotune(10)
         g.init()
         grids.append(g)
     cells = sum(c.ncell for c in cases)
