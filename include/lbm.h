@@ -142,8 +142,10 @@ int lbm_lattice(int32_t q, int32_t *cx, int32_t *cy, double *w, double *T0);
  * Computes the geometry (tangent basis by central differences, metric,
  * volume J, co-tangents, discrete Christoffel sums) in FP64 on the GPU, builds
  * the step tables and allocates the double-buffered populations.  Errors:
- * LBM_EINVAL (q, sizes, halo < c_max + 1, n1 < c_max with walls, tau <= 1/2,
- * J <= 0 anywhere, unpaired periodic side), LBM_ENOMEM, LBM_EDEVICE. */
+ * LBM_EINVAL (q, sizes: n1 n2 > 2^30 cells, n1 + 2 halo > 65535 or a
+ * population buffer of 2 GiB or more; halo < c_max + 1, n1 < c_max with
+ * walls, tau <= 1/2, J <= 0 anywhere, unpaired periodic side, unknown
+ * precision, geometry mode or boundary kind), LBM_ENOMEM, LBM_EDEVICE. */
 int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out);
 void lbm_grid_destroy(lbm_grid *g);
 const char *lbm_last_error(const lbm_grid *g);

@@ -328,6 +328,9 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     if (D.geometry != LBM_GEOM_AUTO && D.geometry != LBM_GEOM_CELL && D.geometry != LBM_GEOM_CELL_TABLE)
         return fail(nullptr, LBM_EINVAL, "unknown geometry mode");
     if ((int64_t)D.n1 * D.n2 > (int64_t)1 << 30) return fail(nullptr, LBM_EINVAL, "grid too large");
+    // the set-up kernels launch one grid row of threads per mapping row
+    if ((int64_t)D.n1 + 2 * (int64_t)D.halo > 65535)
+        return fail(nullptr, LBM_EINVAL, "n1 + 2 halo must not exceed 65535");
     {   // one population buffer must stay below 2 GiB (32-bit buffer offsets)
         const int64_t pitch = D.n2 >= 64 ? (D.n2 + 63) / 64 * 64 : D.n2;
         if ((int64_t)D.q * D.n1 * pitch * (D.precision == LBM_FP64 ? 8 : 4) >= ((int64_t)1 << 31))

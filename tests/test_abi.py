@@ -60,6 +60,7 @@ def _desc_case(**kw):
     (dict(q=15), "unknown lattice"),
     (dict(n1=16384, n2=2048), "population buffer of 2 GiB or more"),
     (dict(n1=1 << 16, n2=1 << 15), "more than 2^30 cells"),
+    (dict(n1=70000, n2=4), "n1 + 2 halo above 65535 (set-up launch rows)"),
 ])
 def test_create_rejects_shapes(lib, kw, what):
     with pytest.raises(lbm.LbmError) as e:
