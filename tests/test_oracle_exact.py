@@ -171,3 +171,29 @@ def test_circular_q21_converges(prob):
         errs.append(np.abs(uth - sol(r)).max() / 0.05)
     assert errs[0] > errs[1] > errs[2], errs
     assert errs[2] < 0.02
+
+
+def test_q9_polar_period2_mode_grows():
+    """D2Q9's neutral period-2 mode (eigenvalue -1 on a uniform grid) is pushed
+    outside the unit circle by the lagged inertial force on polar grids.  On
+    the theta-reduced circular Couette flow (NCR = 2, Nr = 8, tau = 1) the
+    period-2 component of the state, N(t) - 2 N(t+1) + N(t+2), keeps growing
+    where D2Q21 converges (test_circular_q21_converges), so the D2Q9 circular
+    flows overflow instead of settling on a wrong profile."""
+    c, _ = _circ(9, 8, "couette")
+    o = oracle.OracleGrid(c)
+    o.init(1.0)
+
+    def period2():
+        P0 = o.get_state().copy()
+        o.step(1)
+        P1 = o.get_state().copy()
+        o.step(1)
+        P2 = o.get_state().copy()
+        return np.abs(P0 - 2 * P1 + P2).max()
+
+    o.step(1000)
+    a = period2()
+    o.step(248)
+    b = period2()
+    assert np.isfinite(b) and b > 1.5 * a > 0, (a, b)
