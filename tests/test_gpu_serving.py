@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 from gpu_util import say
+from paper_2301_01868_amd import grids as G
 from paper_2301_01868_amd import lbm
 from paper_2301_01868_amd import serve
 
@@ -36,3 +37,23 @@ def test_admission_respects_budget():
     srv = serve.Server(hbm_budget=2 * one, check_every=100)
     srv.run(trace, realtime=False)
     assert all(r.status in ("converged", "unstable") for r in trace)
+
+
+def test_unstable_request_is_isolated():
+    """A request whose state overflows (the 16 x 128 channel stretched by 1.02
+    per cell, whose wall cells leave the lattice's stable band and overflow
+    within about 200 steps) is retired as unstable; the requests running
+    beside it in the same batches converge to exactly the results they get
+    alone."""
+    trace = serve.make_trace(seed=9, rate=400.0, duration=0.02, n_min=16, n_max=24, tol=1e-6)
+    bad = serve.Request(rid=len(trace), arrival=0.0, case=G.workload_planar_poiseuille(128, 0.6), tol=1e-6)
+    mixed = trace + [bad]
+    serve.Server(hbm_budget=64 << 20, check_every=100).run(mixed, realtime=False)
+    say("statuses", [r.status for r in mixed])
+    assert bad.status == "unstable"
+    for r in trace:
+        alone = serve.Request(rid=r.rid, arrival=0.0, case=r.case, tol=r.tol)
+        serve.Server(hbm_budget=64 << 20, check_every=100).run([alone], realtime=False)
+        assert alone.status == r.status and alone.steps == r.steps
+        if r.status == "converged":
+            assert np.array_equal(alone.result["Ut"], r.result["Ut"])
