@@ -95,11 +95,11 @@ struct InstDesc {
 };
 
 // Element index of population a of cell (i, j) in a population buffer.  Each
-// row holds column blocks, each block its Q direction segments.  FP32 storage
-// uses blocks of 64 columns (bs = 6: a wave's pulls and stores touch a few
-// contiguous blocks); FP64 and FP16 storage, and rows narrower than 64, use
-// one block per row (bs = 30: [row][direction][column]).  Each choice was
-// the faster one measured for its storage type.
+// row holds column blocks, each block its Q direction segments.  FP32 and FP64
+// storage use blocks of 64 columns (bs = 6: a wave's pulls and stores touch a
+// few contiguous blocks); FP16 storage, and rows narrower than 64, use one
+// block per row (bs = 30: [row][direction][column]).  Each choice was the
+// faster one measured for its storage type.
 __host__ __device__ inline size_t pidx(const InstDesc *d, int a, int i, int j)
 {
     return (size_t)i * d->sr + (size_t)(j >> d->bs) * d->sb + (size_t)a * d->sa + (size_t)(j & d->bm);
@@ -624,7 +624,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
     if (interior && nowrap) {
         // the whole stencil of the wave stays inside: source (i - c1, j - c2),
         // same direction
-        if constexpr (sizeof(S) == 4) {
+        if constexpr (sizeof(S) >= 4) {
             // 64-column blocks (the fast path needs n2 > 64, so bs = 6):
             // column j - c2 lies in block j0/64 - 1, j0/64 or j0/64 + 1
             // (j0 >= 64 here); one per-lane offset per shift c2, counted from
@@ -645,7 +645,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
                 if constexpr (CT == 0) n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             }
         } else {
-            // one block per row: the column shift rides in the scalar offset
+            // one block per row (FP16): the column shift rides in the scalar offset
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
                 const uint32_t soff = (uint32_t)((int)(a * sa_b + (i - cx(a)) * sr_b) - cy(a) * (int)ES);

@@ -512,11 +512,11 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     I.mB64 = g->mB64;
     I.plane = (long long)plane;
     // populations [row][column block][direction][block width] (pidx): FP32
-    // rows in blocks of 64 columns, FP64/FP16 rows (and rows narrower than
-    // 64) as one block, the faster layout measured for each storage type;
-    // the two force sums [row][2][column]
+    // and FP64 rows in blocks of 64 columns, FP16 rows (and rows narrower
+    // than 64) as one block, the faster layout measured for each storage
+    // type; the two force sums [row][2][column]
     {
-        const bool blocks = g->precision == LBM_FP32 && g->pitch >= 64;
+        const bool blocks = g->precision != LBM_FP16 && g->pitch >= 64;
         const int bw = blocks ? 64 : g->pitch;
         I.bs = blocks ? 6 : 30;
         I.bm = (1 << I.bs) - 1;
