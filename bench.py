@@ -1,6 +1,11 @@
 """Throughput benchmark of the curvilinear lattice Boltzmann step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision fp32|fp64]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                [--geometry auto|cell|cell_table] [--iterations K] [--no-fp64] [--no-fp16] [--no-cpu]
+python bench.py --serve [--rate R] [--duration S] [--no-sequential]
+
+FP32 populations give the headline figure; the same workload is then timed
+with FP64 and FP16 populations (reported under "fp64" and "fp16").
 
 A step is one application of the whole fused update (pull streaming with the
 wall sources, moments, lagged inertial force, equilibrium, momentum-flux and
