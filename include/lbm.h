@@ -138,6 +138,31 @@ typedef struct {
  * weights w[q], T0.  Returns LBM_EINVAL for q other than 9 or 21. */
 int lbm_lattice(int32_t q, int32_t *cx, int32_t *cy, double *w, double *T0);
 
+/* Mapping helpers (host only): the halo-extended cell centres x, y
+ * [(n1 + 2 halo)(n2 + 2 halo)], q2 fastest, that lbm_grid_create takes, for
+ * the paper's two grid families.  Rows run along q1 (wall-normal), defined by
+ * the n1 + 1 strictly increasing face positions faces[0..n1] (lattice units:
+ * uniform, the linear contraction of App. C, geometric stretching ...); cell
+ * centres are the face midpoints.  The halo rows beyond each wall hold the
+ * symmetrically continued geometry of Sec. 3.1: row 1 - k is the mirror image
+ * of row k across the low wall (faces[0]) and row n1 + k that of row
+ * n1 + 1 - k across the high wall (faces[n1]), repeated when halo > n1.  The
+ * periodic q2 direction continues the mapping.  halo: 1..64.  Errors:
+ * LBM_EINVAL (null pointer, sizes, faces not finite or not increasing, and the
+ * family's own conditions below), with the text in lbm_last_error(NULL).
+ *
+ * lbm_map_planar: planar channel (Sec. 3.1, App. C); x = the wall-normal
+ * position, y = (j + 1/2) d_per for columns j = -halo .. n2 + halo - 1;
+ * d_per > 0.
+ *
+ * lbm_map_polar: annulus on the half-spaced polar lattice of App. D; faces
+ * are radii, theta_j = (j + 1/2) 2 pi / ntheta, x = r cos theta,
+ * y = r sin theta.  n2 <= ntheta columns are kept (n2 < ntheta: a theta
+ * reduction, exact for theta-invariant states); every ring, ghosts included,
+ * must have r > 0. */
+int lbm_map_planar(int32_t n1, int32_t n2, int32_t halo, const double *faces, double d_per, double *x, double *y);
+int lbm_map_polar(int32_t n1, int32_t n2, int32_t halo, const double *r_faces, int32_t ntheta, double *x, double *y);
+
 /* Create a grid from a coordinate mapping (Sec. 2, Eqs. distance..gamma).
  * Computes the geometry (tangent basis by central differences, metric,
  * volume J, co-tangents, discrete Christoffel sums) in FP64 on the GPU, builds

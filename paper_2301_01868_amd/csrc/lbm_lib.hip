@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_maps.hpp"
 #include "lbm_setup.hpp"
 
 using namespace lbm;
@@ -287,6 +288,18 @@ int lbm_lattice(int32_t q, int32_t *cxo, int32_t *cyo, double *w, double *T0)
     }
     if (T0) *T0 = q == 9 ? lattice_T0<9>() : lattice_T0<21>();
     return LBM_OK;
+}
+
+int lbm_map_planar(int32_t n1, int32_t n2, int32_t halo, const double *faces, double d_per, double *x, double *y)
+{
+    std::string e = lbm_maps::map_planar(n1, n2, halo, faces, d_per, x, y);
+    return e.empty() ? LBM_OK : fail(nullptr, LBM_EINVAL, "lbm_map_planar: " + e);
+}
+
+int lbm_map_polar(int32_t n1, int32_t n2, int32_t halo, const double *r_faces, int32_t ntheta, double *x, double *y)
+{
+    std::string e = lbm_maps::map_polar(n1, n2, halo, r_faces, ntheta, x, y);
+    return e.empty() ? LBM_OK : fail(nullptr, LBM_EINVAL, "lbm_map_polar: " + e);
 }
 
 const char *lbm_last_error(const lbm_grid *g)

@@ -26,7 +26,7 @@ EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_erro
             "lbm_set_volume", "lbm_get_volume", "lbm_init", "lbm_step", "lbm_moments", "lbm_residual", "lbm_noflow_adjust",
             "lbm_get_state", "lbm_set_state", "lbm_save", "lbm_load", "lbm_physical_velocity", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
             "lbm_stream", "lbm_batch_create", "lbm_batch_create_ex", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_set_occupancy", "lbm_autotune",
-            "lbm_copy_probe", "lbm_bandwidth_probe"]
+            "lbm_copy_probe", "lbm_bandwidth_probe", "lbm_map_planar", "lbm_map_polar"]
 
 
 class LbmError(RuntimeError):
@@ -116,6 +116,8 @@ def load():
     L.lbm_autotune.argtypes = [vp, ct.c_int32]
     L.lbm_copy_probe.argtypes = [vp, vp, ct.c_size_t, vp]
     L.lbm_bandwidth_probe.argtypes = [vp, vp, ct.c_size_t, ct.c_int32, vp]
+    L.lbm_map_planar.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, D, ct.c_double, D, D]
+    L.lbm_map_polar.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, D, ct.c_int32, D, D]
     _lib = L
     return L
 
@@ -140,6 +142,27 @@ def lbm_lattice(q):
     T0 = ct.c_double()
     _chk(load().lbm_lattice(q, cx, cy, _dp(w), ct.byref(T0)))
     return np.stack([np.array(cx[:]), np.array(cy[:])], 1), w, T0.value
+
+
+def lbm_map_planar(faces, n2, halo, d_per=1.0):
+    """Halo-extended cell centres (X, Y) of a planar channel, shape (n1 + 2 halo, n2 + 2 halo)."""
+    f = np.ascontiguousarray(faces, dtype=np.float64)
+    n1 = len(f) - 1
+    X = np.empty((n1 + 2 * halo, n2 + 2 * halo))
+    Y = np.empty_like(X)
+    _chk(load().lbm_map_planar(n1, n2, halo, _dp(f), d_per, _dp(X), _dp(Y)))
+    return X, Y
+
+
+def lbm_map_polar(r_faces, ntheta, halo, n2=None):
+    """Halo-extended cell centres (X, Y) of an annulus on the half-spaced polar lattice."""
+    f = np.ascontiguousarray(r_faces, dtype=np.float64)
+    n1 = len(f) - 1
+    n2 = ntheta if n2 is None else n2
+    X = np.empty((n1 + 2 * halo, n2 + 2 * halo))
+    Y = np.empty_like(X)
+    _chk(load().lbm_map_polar(n1, n2, halo, _dp(f), ntheta, _dp(X), _dp(Y)))
+    return X, Y
 
 
 def lbm_grid_create(case, precision=LBM_FP64, offset_base=LBM_BASE_LOCAL_REST, iterations=0,
