@@ -107,11 +107,16 @@ def test_header_is_c_and_links_from_c(lib, tmp_path):
         "    (void)d; (void)r; (void)info;\n"
         "    if (lbm_lattice(21, cx, cy, w, &T0) != LBM_OK) return 1;\n"
         "    if (lbm_lattice(15, cx, cy, w, &T0) != LBM_EINVAL) return 2;\n"
-        '    printf("%.17g %d %d\\n", T0, cx[17], cy[18]);\n'
+        "    double f[4] = {0.0, 1.0, 2.0, 3.0}, x[11 * 10], y[11 * 10];\n"
+        "    if (lbm_map_planar(3, 2, 4, f, 0.5, x, y) != LBM_OK) return 3;\n"
+        "    if (lbm_map_planar(3, 2, 4, f, -1.0, x, y) != LBM_EINVAL) return 4;\n"
+        '    printf("%.17g %d %d %.17g %.17g\\n", T0, cx[17], cy[18], x[0], y[10 * 10 - 1]);\n'
         "    return 0;\n}\n")
     exe = tmp_path / "abi"
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
                            os.path.join(ROOT, "include"), "-o", str(exe), str(src), lbm.LIB_PATH,
                            "-Wl,-rpath," + os.path.dirname(lbm.LIB_PATH)])
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    assert float(out[0]) == 2.0 / 3.0 and out[1:] == ["3", "3"]
+    assert float(out[0]) == 2.0 / 3.0 and out[1:3] == ["3", "3"]
+    # first ghost row of a 3-cell channel with halo 4 (rows -3..6 at x = 1/2 + integer); y of the last column
+    assert float(out[3]) == -3.5 and float(out[4]) == (5 + 0.5) * 0.5
