@@ -147,6 +147,10 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
         grids.append(g)
     cells = sum(c.ncell for c in cases)
     batch = lbm.lbm_batch_create([g.h for g in grids]) if len(grids) > 1 else None
+    if batch is not None:
+        # each group's launch shape timed on the whole group (the per-grid choices above
+        # serve the one-grid-at-a-time comparison); the trials advance every grid alike
+        lbm.lbm_batch_autotune(batch, 20)
 
     def run(n):
         if batch is not None:
@@ -172,6 +176,7 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
     sname = {8: "f64", 4: "f32", 2: "f16"}[s_bytes]
     kind = {0: "row", 1: "cell tables", 2: "cell geometry"}[grids[0].info.table_kind]
     if batch is None:
+        launch = (grids[0].info.waves_per_block, grids[0].info.waves_per_cu_cap)
         q = cases[0].q
         kcells = cells
         avg_ms = ms / steps
@@ -189,12 +194,14 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
         torch.cuda.synchronize()
         avg_ms = ev0.elapsed_time(ev1) / reps
         kname = "k_step<%d,%s,%s> (batch group of %d cells)" % (q, sname, kind, kcells)
+        launch = lbm.lbm_batch_group_launch(batch, gi)
     alg_bytes = 2 * q * s_bytes * kcells
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     traffic = recorded_traffic(workload, sname, kcells) if (workload and iterations == 0 and geometry == 0) else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-            "bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_ms * 1e3, 3)}
+            "bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_ms * 1e3, 3),
+            "launch": {"waves_per_block": launch[0], "waves_per_cu_cap": launch[1]}}
     if traffic:
         roof["traffic_GBps"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
     seq = None

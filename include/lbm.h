@@ -282,6 +282,21 @@ int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *preci
  * batch's states are no longer one consistent time level afterwards. */
 int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n);
 
+/* Autotuner for a batch: for each group, times `steps` launches (rounded up
+ * to even, after 2 untimed ones) of the group's own step kernel over all of
+ * its tiles for each tile shape (1, 2 or 4 rows per workgroup) and each
+ * occupancy cap (none, 24, 20 or 16 waves per CU), and keeps the fastest pair
+ * for that group (until then a group launches with the choice of its first
+ * grid).  The trials step the batch's own state: every grid advances by the
+ * same even number of steps, 12 (steps + 2), exactly as lbm_batch_step would
+ * have advanced it, since no result depends on the launch shape.  Step
+ * counters advance accordingly.  Synchronises; LBM_EINVAL for a null batch. */
+int lbm_batch_autotune(lbm_batch *b, int32_t steps);
+
+/* Launch shape of batch group g: waves (rows) per workgroup and the resident
+ * waves per CU cap (0 = none).  LBM_EINVAL when g is out of range. */
+int lbm_batch_group_launch(const lbm_batch *b, int32_t group, int32_t *waves_per_block, int32_t *waves_per_cu_cap);
+
 /* Launch configuration of the step kernels for a grid (and the batches made
  * from it later): waves per workgroup (1, 2 or 4; each wave covers 64
  * columns of one row; 0 = default 4). */

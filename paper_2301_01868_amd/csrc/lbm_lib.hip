@@ -75,6 +75,7 @@ struct lbm_batch {
         InstDesc *d_inst = nullptr;
         int4 *d_tiles = nullptr;
         int ntiles = 0, wpb = 4, cap = 0;
+        std::vector<int> members;      // indices into grids
     };
     std::vector<Group> groups;
     std::vector<void *> allocs;
@@ -1150,6 +1151,38 @@ void lbm_batch_destroy(lbm_batch *b)
     delete b;
 }
 
+// Tile table of a batch group for `wpb` rows per workgroup: the members'
+// tiles (instance = position in the group) in the XCD-run order, uploaded
+// to a device allocation the batch owns.
+static int group_tiles(lbm_batch *b, const std::vector<int> &members, int wpb, int4 **d_out, int *nt_out)
+{
+    std::vector<int4> nat;
+    int inst = 0;
+    for (int k : members) {
+        const lbm_grid *g = b->grids[k];
+        auto t = make_tiles(inst++, g->n1, g->n2, wpb, g->q);
+        nat.insert(nat.end(), t.begin(), t.end());
+    }
+    // largest instances' tiles first would help tail balance; keep the
+    // natural order (instances contiguous) so each XCD works on few grids
+    auto ord = xcd_order(nat, 1 << 30);
+    void *dt = nullptr;
+    if (hipMalloc(&dt, ord.size() * sizeof(int4)) != hipSuccess) return fail(nullptr, LBM_ENOMEM, "batch allocation failed");
+    b->allocs.push_back(dt);
+    if (hipMemcpy(dt, ord.data(), ord.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(nullptr, LBM_EDEVICE, "batch upload failed");
+    *d_out = (int4 *)dt;
+    *nt_out = (int)ord.size();
+    return LBM_OK;
+}
+
+static void batch_free(lbm_batch *b, void *p)
+{
+    auto it = std::find(b->allocs.begin(), b->allocs.end(), p);
+    if (it != b->allocs.end()) b->allocs.erase(it);
+    (void)hipFree(p);
+}
+
 int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
 {
     return lbm_batch_create_ex(grids, n, 0u, out);
@@ -1190,36 +1223,30 @@ int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_b
         G.iter = std::get<3>(kv.first);
         G.wpb = b->grids[kv.second[0]]->wpb;
         G.cap = b->grids[kv.second[0]]->cap;
+        G.members = kv.second;
         std::vector<InstDesc> descs;
-        std::vector<int4> nat;
         for (int k : kv.second) {
             lbm_grid *g = b->grids[k];
             InstDesc I = g->h_inst;
             I.par0 = g->par;
-            const int inst = (int)descs.size();
             descs.push_back(I);
-            auto t = make_tiles(inst, g->n1, g->n2, G.wpb, g->q);
-            nat.insert(nat.end(), t.begin(), t.end());
         }
-        // largest instances' tiles first would help tail balance; keep the
-        // natural order (instances contiguous) so each XCD works on few grids
-        auto ord = xcd_order(nat, 1 << 30);
-        void *di = nullptr, *dt = nullptr;
-        if (hipMalloc(&di, descs.size() * sizeof(InstDesc)) != hipSuccess ||
-            hipMalloc(&dt, ord.size() * sizeof(int4)) != hipSuccess) {
+        void *di = nullptr;
+        if (hipMalloc(&di, descs.size() * sizeof(InstDesc)) != hipSuccess) {
             lbm_batch_destroy(b);
             return fail(nullptr, LBM_ENOMEM, "batch allocation failed");
         }
         b->allocs.push_back(di);
-        b->allocs.push_back(dt);
-        if (hipMemcpy(di, descs.data(), descs.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(dt, ord.data(), ord.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) {
+        if (hipMemcpy(di, descs.data(), descs.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess) {
             lbm_batch_destroy(b);
             return fail(nullptr, LBM_EDEVICE, "batch upload failed");
         }
         G.d_inst = (InstDesc *)di;
-        G.d_tiles = (int4 *)dt;
-        G.ntiles = (int)ord.size();
+        const int rc = group_tiles(b, G.members, G.wpb, &G.d_tiles, &G.ntiles);
+        if (rc != LBM_OK) {
+            lbm_batch_destroy(b);
+            return rc;
+        }
         b->groups.push_back(G);
     }
     if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) {
@@ -1355,6 +1382,86 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n)
         hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), step_lds(G.cell, G.q, G.precision, G.cap, G.wpb), b->stream, (const InstDesc *)G.d_inst,
                            (const int4 *)G.d_tiles, (int)((b->step + k) & 1));
     if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "group step launch failed");
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch *b, int32_t steps)
+{
+    if (!b) return fail(nullptr, LBM_EINVAL, "null batch");
+    if (steps < 2) steps = 2;
+    steps += steps & 1;                 // even, so every trial keeps the buffer parity
+    const int64_t per_trial = 2 + (int64_t)steps;
+    int rc = batch_join_in(b);
+    if (rc != LBM_OK) return rc;
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events()
+        {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    if (hipEventCreate(&ev.e0) != hipSuccess || hipEventCreate(&ev.e1) != hipSuccess)
+        return fail(nullptr, LBM_EDEVICE, "event creation failed");
+    const int shapes[3] = {4, 2, 1}, caps[4] = {0, 24, 20, 16};
+    int64_t advanced = 0;
+    for (auto &G : b->groups) {
+        int4 *tiles[3] = {nullptr, nullptr, nullptr};
+        int nts[3] = {0, 0, 0};
+        for (int s = 0; s < 3; ++s) {
+            if (shapes[s] == G.wpb) {
+                tiles[s] = G.d_tiles;
+                nts[s] = G.ntiles;
+            } else if ((rc = group_tiles(b, G.members, shapes[s], &tiles[s], &nts[s])) != LBM_OK) {
+                return rc;
+            }
+        }
+        StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter);
+        int best_s = 0, best_c = 0;
+        float best_ms = 1e30f;
+        int64_t k = b->step;            // this group's grids are at the batch's time level
+        for (int s = 0; s < 3; ++s)
+            for (int c : caps) {
+                const unsigned lds = step_lds(G.cell, G.q, G.precision, c, shapes[s]);
+                for (int64_t t = 0; t < per_trial; ++t, ++k) {
+                    if (t == 2 && hipEventRecord(ev.e0, b->stream) != hipSuccess)
+                        return fail(nullptr, LBM_EDEVICE, "event record failed");
+                    hipLaunchKernelGGL(fn, dim3(nts[s]), dim3(64 * shapes[s]), lds, b->stream, (const InstDesc *)G.d_inst,
+                                       (const int4 *)tiles[s], (int)(k & 1));
+                }
+                if (hipGetLastError() != hipSuccess) return fail(nullptr, LBM_EDEVICE, "trial launch failed");
+                float ms = 0.f;
+                if (hipEventRecord(ev.e1, b->stream) != hipSuccess || hipEventSynchronize(ev.e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess)
+                    return fail(nullptr, LBM_EDEVICE, "trial timing failed");
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_s = s;
+                    best_c = c;
+                }
+            }
+        advanced = k - b->step;         // the same for every group
+        for (int s = 0; s < 3; ++s)
+            if (s != best_s) batch_free(b, tiles[s]);
+        G.wpb = shapes[best_s];
+        G.cap = best_c;
+        G.d_tiles = tiles[best_s];
+        G.ntiles = nts[best_s];
+    }
+    // every grid advanced by the same even number of steps, as lbm_batch_step would have moved it
+    b->step += advanced;
+    for (lbm_grid *g : b->grids) g->step += advanced;
+    if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
+    b->graph.exec = nullptr;
+    b->graph.steps = 0;
+    return batch_join_out(b);
+}
+
+int lbm_batch_group_launch(const lbm_batch *b, int32_t group, int32_t *waves_per_block, int32_t *waves_per_cu_cap)
+{
+    if (!b || group < 0 || group >= (int32_t)b->groups.size()) return fail(nullptr, LBM_EINVAL, "no such group");
+    if (waves_per_block) *waves_per_block = b->groups[group].wpb;
+    if (waves_per_cu_cap) *waves_per_cu_cap = b->groups[group].cap;
     return LBM_OK;
 }
 

@@ -26,7 +26,8 @@ EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_erro
             "lbm_set_volume", "lbm_get_volume", "lbm_init", "lbm_step", "lbm_moments", "lbm_residual", "lbm_noflow_adjust",
             "lbm_get_state", "lbm_set_state", "lbm_save", "lbm_load", "lbm_physical_velocity", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
             "lbm_stream", "lbm_batch_create", "lbm_batch_create_ex", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_set_occupancy", "lbm_autotune",
-            "lbm_copy_probe", "lbm_bandwidth_probe", "lbm_map_planar", "lbm_map_polar"]
+            "lbm_copy_probe", "lbm_bandwidth_probe", "lbm_map_planar", "lbm_map_polar",
+            "lbm_batch_autotune", "lbm_batch_group_launch"]
 
 
 class LbmError(RuntimeError):
@@ -116,6 +117,8 @@ def load():
     L.lbm_autotune.argtypes = [vp, ct.c_int32]
     L.lbm_copy_probe.argtypes = [vp, vp, ct.c_size_t, vp]
     L.lbm_bandwidth_probe.argtypes = [vp, vp, ct.c_size_t, ct.c_int32, vp]
+    L.lbm_batch_autotune.argtypes = [vp, ct.c_int32]
+    L.lbm_batch_group_launch.argtypes = [vp, ct.c_int32, I32, I32]
     L.lbm_map_planar.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, D, ct.c_double, D, D]
     L.lbm_map_polar.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, D, ct.c_int32, D, D]
     _lib = L
@@ -358,6 +361,18 @@ def lbm_batch_groups(b):
     if n < 0:
         _chk(n)
     return [lbm_batch_info(b, k)[1:] for k in range(n)]
+
+
+def lbm_batch_autotune(b, steps=20):
+    _chk(load().lbm_batch_autotune(b, steps))
+
+
+def lbm_batch_group_launch(b, group):
+    """(waves per workgroup, waves-per-CU cap) of a batch group's step launch."""
+    w = ct.c_int32()
+    c = ct.c_int32()
+    _chk(load().lbm_batch_group_launch(b, group, ct.byref(w), ct.byref(c)))
+    return w.value, c.value
 
 
 def lbm_batch_step_group(b, group, n):

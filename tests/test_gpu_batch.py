@@ -46,6 +46,40 @@ def test_batch_equals_alone(prec):
         assert np.array_equal(sa, sm)
 
 
+@pytest.mark.parametrize("fuse", [0, lbm.LBM_BATCH_FUSE_LATTICES], ids=["per_lattice", "fused"])
+def test_batch_autotune_advances_like_steps(fuse):
+    """The batch autotuner's trial launches advance every grid by the same even
+    number of steps; afterwards the batch ends exactly where plain steps end."""
+    cases = _cases()
+    tuned = [lbm.Grid(c, precision=lbm.LBM_FP32) for c in cases]
+    plain = [lbm.Grid(c, precision=lbm.LBM_FP32) for c in cases]
+    for g in tuned + plain:
+        g.set_launch(1)         # the group starts from a shape the tuner may replace
+        g.init()
+    tuned[1].step(3)            # one grid on the other buffer parity
+    plain[1].step(3)
+    bt = lbm.lbm_batch_create_ex([g.h for g in tuned], fuse)
+    s0 = [g.info.step for g in tuned]
+    lbm.lbm_batch_autotune(bt, 3)                     # rounded up to 4: 12 x 6 = 72 steps
+    adv = [g.info.step - s for g, s in zip(tuned, s0)]
+    say("autotune advanced", adv, "shapes", [lbm.lbm_batch_group_launch(bt, k) for k in range(len(lbm.lbm_batch_groups(bt)))])
+    assert adv == [72] * len(cases)
+    for k in range(len(lbm.lbm_batch_groups(bt))):
+        w, c = lbm.lbm_batch_group_launch(bt, k)
+        assert w in (1, 2, 4) and c in (0, 16, 20, 24)
+    lbm.lbm_batch_step(bt, 41)
+    bp = lbm.lbm_batch_create_ex([g.h for g in plain], fuse)
+    lbm.lbm_batch_step(bp, 72 + 41)
+    lbm.lbm_batch_destroy(bt)
+    lbm.lbm_batch_destroy(bp)
+    for gt, gp, c in zip(tuned, plain, cases):
+        assert gt.info.step == gp.info.step
+        Pt, st = gt.get_state()
+        Pp, sp = gp.get_state()
+        assert np.array_equal(Pt, Pp), c.meta
+        assert np.array_equal(st, sp)
+
+
 @pytest.mark.parametrize("prec", [lbm.LBM_FP64, lbm.LBM_FP32, lbm.LBM_FP16], ids=["fp64", "fp32", "fp16"])
 def test_fused_lattice_batch_equals_alone(prec):
     """D2Q9 and D2Q21 grids in one fused launch per step end exactly as alone."""
