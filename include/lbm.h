@@ -290,7 +290,9 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n);
  * grid).  The trials step the batch's own state: every grid advances by the
  * same even number of steps, 12 (steps + 2), exactly as lbm_batch_step would
  * have advanced it, since no result depends on the launch shape.  Step
- * counters advance accordingly.  Synchronises; LBM_EINVAL for a null batch. */
+ * counters advance accordingly.  Synchronises; LBM_EINVAL for a null batch,
+ * LBM_ENOMEM / LBM_EDEVICE if a trial's tile table or launch fails (the
+ * grids' states are then not at one time level: initialise them again). */
 int lbm_batch_autotune(lbm_batch *b, int32_t steps);
 
 /* Launch shape of batch group g: waves (rows) per workgroup and the resident
