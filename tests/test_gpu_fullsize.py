@@ -161,3 +161,37 @@ def test_ensemble_smallest_full_horizon():
         err = np.abs((col[:, 1] - Uto[:, 1]) * c.meta["centres"] * np.sin(c.meta["dtheta"])).max() / 0.05
         say("instance", k, "Q%d" % c.q, "%dx%d" % (c.n1, c.n2), "u_theta err / U", err)
         assert err <= 1e-5, (k, err)
+
+
+@pytest.mark.parametrize("prec,n1,n2,tol1", [(lbm.LBM_FP32, 2048, 12480, 3e-6), (lbm.LBM_FP64, 1024, 12480, 1e-13)],
+                         ids=["fp32", "fp64"])
+def test_largest_accepted_grid(prec, n1, n2, tol1):
+    """The largest population buffer the library accepts: 21 x n1 x pitch
+    values just under 2 GiB (2,146,959,360 bytes), the reach of the step's
+    32-bit buffer offsets.  One step from a sheared state against the oracle
+    on sampled cells (every wall-adjacent row, so the buffer's last rows too);
+    one more column block is rejected at create."""
+    case = G.circular_couette(21, n1, n2, float(n1), u_inner=0.05, tau=0.8)
+    say("largest grid", n1, "x", n2, "prec", prec)
+    s = 8 if prec == lbm.LBM_FP64 else 4
+    assert 21 * n1 * n2 * s == 2_146_959_360 < 2 ** 31
+    bigger = G.circular_couette(21, n1, n2 + 1, float(n1), u_inner=0.05, tau=0.8)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Grid(bigger, precision=prec)
+    assert e.value.code == lbm.LBM_EINVAL
+    del bigger
+    g = lbm.Grid(case, precision=prec)
+    assert g.info.row_tables == 1
+    i = (np.arange(n1)[:, None] + 0.5) / n1
+    j = (np.arange(n2)[None, :] + 0.5) / n2
+    u0 = np.zeros((n1, n2, 2))
+    u0[..., 1] = 0.01 * (1.0 + i) * np.sin(2 * np.pi * 7 * j)
+    g.init(u0.reshape(-1, 2))
+    del u0
+    g.step(3)
+    r = g.residual(check=False)
+    assert r.bad_cells == 0
+    e1 = _one_step_sampled(g, case, nsample=3000)
+    say("largest grid one-step sampled rel err", e1)
+    assert e1 <= tol1
+    g.close()
