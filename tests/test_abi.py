@@ -89,6 +89,10 @@ def test_null_arguments_are_rejected(lib):
     assert lib.lbm_init(None, None) == lbm.LBM_EINVAL
     assert lib.lbm_step(None, ct.c_int64(1)) == lbm.LBM_EINVAL
     assert lib.lbm_set_occupancy(None, 0) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_autotune(None, 10) == lbm.LBM_EINVAL
+    w, c = ct.c_int32(), ct.c_int32()
+    assert lib.lbm_batch_group_launch(None, 0, ct.byref(w), ct.byref(c)) == lbm.LBM_EINVAL
+    assert lib.lbm_map_planar(3, 2, 2, None, 1.0, None, None) == lbm.LBM_EINVAL
 
 
 def test_header_is_c_and_links_from_c(lib, tmp_path):
