@@ -80,6 +80,40 @@ def test_batch_autotune_advances_like_steps(fuse):
         assert np.array_equal(st, sp)
 
 
+def test_batch_autotune_per_cell_and_iterated_groups():
+    """Autotuning groups of per-cell geometry (LDS-staged) and fixed-point force
+    grids also leaves the batch where plain steps leave it."""
+    specs = [(G.periodic_box(21, 9, 70, dx=1.0, dy=1.1, skew=0.1, wobble=0.25, tau=0.9), 0),
+             (G.periodic_box(21, 12, 130, dx=1.0, dy=1.1, skew=0.1, wobble=0.2, tau=0.8), 0),
+             (G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, tau=0.8), 1),
+             (G.circular_poiseuille(9, 10, 70, 12.0, g2=1e-4, tau=0.7), 0)]
+
+    def make():
+        gs = [lbm.Grid(c, precision=lbm.LBM_FP32, iterations=k) for c, k in specs]
+        for g in gs:
+            g.init()
+        return gs
+
+    tuned, plain = make(), make()
+    assert tuned[0].info.table_kind == 2
+    bt = lbm.lbm_batch_create([g.h for g in tuned])
+    ngroups = len(lbm.lbm_batch_groups(bt))
+    assert ngroups == 3
+    lbm.lbm_batch_autotune(bt, 2)                     # 12 x 4 = 48 steps
+    say("per-cell / iterated autotune shapes", [lbm.lbm_batch_group_launch(bt, k) for k in range(ngroups)])
+    lbm.lbm_batch_step(bt, 21)
+    bp = lbm.lbm_batch_create([g.h for g in plain])
+    lbm.lbm_batch_step(bp, 48 + 21)
+    lbm.lbm_batch_destroy(bt)
+    lbm.lbm_batch_destroy(bp)
+    for gt, gp in zip(tuned, plain):
+        assert gt.info.step == gp.info.step == 69
+        Pt, st = gt.get_state()
+        Pp, sp = gp.get_state()
+        assert np.array_equal(Pt, Pp)
+        assert np.array_equal(st, sp)
+
+
 @pytest.mark.parametrize("prec", [lbm.LBM_FP64, lbm.LBM_FP32, lbm.LBM_FP16], ids=["fp64", "fp32", "fp16"])
 def test_fused_lattice_batch_equals_alone(prec):
     """D2Q9 and D2Q21 grids in one fused launch per step end exactly as alone."""
