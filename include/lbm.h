@@ -170,7 +170,12 @@ int lbm_map_polar(int32_t n1, int32_t n2, int32_t halo, const double *r_faces, i
  * LBM_EINVAL (q, sizes: n1 n2 > 2^30 cells, n1 + 2 halo > 65535 or a
  * population buffer of 2 GiB or more; halo < c_max + 1, n1 < c_max with
  * walls, tau <= 1/2, J <= 0 anywhere, unpaired periodic side, unknown
- * precision, geometry mode or boundary kind), LBM_ENOMEM, LBM_EDEVICE. */
+ * precision, offset base, geometry mode or boundary kind), LBM_ENOMEM,
+ * LBM_EDEVICE.
+ *
+ * Walls sit on the two q1 sides only, as in App. B (whose reflection rules
+ * are stated for walls normal to q1 with q2 periodic); a problem with walls
+ * across q2 is posed by naming its wall-normal axis q1 in the mapping. */
 int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out);
 void lbm_grid_destroy(lbm_grid *g);
 const char *lbm_last_error(const lbm_grid *g);
@@ -184,21 +189,49 @@ int lbm_set_volume(lbm_grid *g, const double *J);
 /* Volume currently used for initial state and density output, J[n1*n2]. */
 int lbm_get_volume(lbm_grid *g, double *J);
 
-/* Initial state N = J f^eq(rho0, U = Ut = u0; g^ij), which also serves as the
- * lagged N'(q, -1); u0[n1*n2][2] contravariant, or NULL for rest.  Resets the
- * step counter and the residual reference. */
+/* Initial state of Sec. 3.1 (uniform density rho0, fluid at rest or at u0):
+ * N = J f^eq(rho0, U = Ut = u0; g^ij) with the equilibrium of Eq.
+ * (equilibrium), J the grid's current volume (geometric, or J' after the
+ * no-flow adjustment).  The same state serves as the lagged N'(q, -1) that
+ * the force of the first step reads (Eq. compo-constr takes the own cell's
+ * previous post-collision populations; before the first step there are none,
+ * and the initial state is used: a reading, since the paper does not say).
+ * u0[n1*n2][2] contravariant, or NULL for rest.  Resets the step counter and
+ * the residual reference.  Errors: LBM_EINVAL (null grid), LBM_ENOMEM,
+ * LBM_EDEVICE. */
 int lbm_init(lbm_grid *g, const double *u0);
 
-/* Advance n time steps (asynchronous on the grid's stream). */
+/* Advance n time steps (asynchronous on the grid's stream).  One step is
+ * the lattice Boltzmann equation of Eq. (lbe): pull streaming in
+ * computational coordinates (Eq. adv) with the periodic, bounce-back and
+ * moving-wall sources of App. B.1-B.3; moments (Eqs. moments, vcomp); the
+ * inertial force of Eq. (compo-constr) from the Christoffel sums of Eq.
+ * (gamma), with the own cell's previous post-collision populations (the
+ * one-step lag the paper adopts) or `iterations` fixed-point passes of the
+ * implicit relation; the physical velocity Ut = U + J F / (2 m); BGK
+ * relaxation toward the equilibrium of Eq. (equilibrium) (Eq. collide); the
+ * momentum-flux correction of Eq. (delta-flux) and the correction term of
+ * Eq. (deltaN).  Errors: LBM_EINVAL (null grid, n < 0), LBM_ESTATE (before
+ * lbm_init), LBM_EDEVICE (launch or graph failure). */
 int lbm_step(lbm_grid *g, int64_t n);
 
 /* Moments of the current state, computed as the next step would see them
- * (pull, moments, force): m[n1*n2] = sum_alpha N_alpha (= J rho), U and Ut
- * [n1*n2][2] contravariant; any pointer may be NULL.  Synchronises. */
+ * (pull, moments, force): m[n1*n2] = sum_alpha N_alpha (= J rho, Eq.
+ * moments), U[n1*n2][2] = sum_alpha c_alpha N_alpha / m (Eqs. velocity,
+ * vcomp) and the physical velocity Ut = U + J F / (2 m) of Sec. 2, both as
+ * contravariant components (Eq. result maps them to Cartesian ones with the
+ * tangents g_i; lbm_physical_velocity does that).  Any pointer may be NULL.
+ * Synchronises.  Errors: LBM_EINVAL, LBM_ESTATE (before lbm_init),
+ * LBM_EDEVICE. */
 int lbm_moments(lbm_grid *g, double *m, double *U, double *Ut);
 
-/* FP64 residual and diagnostics (see lbm_resid).  Synchronises.  Returns
- * LBM_EUNSTABLE (after filling *out) when bad_cells > 0. */
+/* FP64 residual and diagnostics (see lbm_resid).  Sec. 3.1 runs every flow
+ * to steady state and judges it by the kinetic energy and the conservation
+ * of mass and angular momentum; the paper defines no residual, so
+ * lbm_resid.residual is this library's reading: the relative change of the
+ * momentum m Ut per step since the previous call.  Synchronises.  Returns
+ * LBM_EUNSTABLE (after filling *out) when bad_cells > 0; LBM_EINVAL,
+ * LBM_ESTATE (before lbm_init), LBM_EDEVICE. */
 int lbm_residual(lbm_grid *g, lbm_resid *out);
 
 /* The "no flow" adjustment of Sec. 3.1: from rest, with the grid's boundary

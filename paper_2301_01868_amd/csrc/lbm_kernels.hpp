@@ -484,9 +484,13 @@ struct GeoTab {
                 if ((lo ? bclo : bchi) != BC_NOSLIP) s = -1.0;
             }
             const int dc = -cy(a);
-            const double Js = ld(GE_J, dr, dc);
-            const double Bs = sbase == 0 ? jrest<Q>(a, Js, ld(GE_H11, dr, dc), ld(GE_H12, dr, dc), ld(GE_H22, dr, dc), s)
-                                         : weight<Q>(a) * Js;
+            // storage base of the source: local rest state, J w rho0, or none
+            double Bs = 0.0;
+            if (sbase == 0) {
+                Bs = jrest<Q>(a, ld(GE_J, dr, dc), ld(GE_H11, dr, dc), ld(GE_H12, dr, dc), ld(GE_H22, dr, dc), s);
+            } else if (sbase == 1) {
+                Bs = weight<Q>(a) * ld(GE_J, dr, dc);
+            }
             return (T)(rho0 * (Bs - jrest<Q>(a, J, h11, h12, h22)));
         }
     }
@@ -497,7 +501,8 @@ struct GeoTab {
             return (T)0;
         } else {
             if (sbase == 0) return (T)0;
-            return (T)(rho0 * (jrest<Q>(a, J, h11, h12, h22) - weight<Q>(a) * J));
+            const double Bs = sbase == 1 ? weight<Q>(a) * J : 0.0;
+            return (T)(rho0 * (jrest<Q>(a, J, h11, h12, h22) - Bs));
         }
     }
 

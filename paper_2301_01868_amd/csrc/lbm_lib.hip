@@ -338,6 +338,8 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     if (D.n1 < cm) return fail(nullptr, LBM_EINVAL, "n1 must be at least c_max");
     if (D.precision != LBM_FP64 && D.precision != LBM_FP32 && D.precision != LBM_FP16)
         return fail(nullptr, LBM_EINVAL, "unknown precision");
+    if (D.offset_base != LBM_BASE_LOCAL_REST && D.offset_base != LBM_BASE_W_RHO0 && D.offset_base != LBM_BASE_NONE)
+        return fail(nullptr, LBM_EINVAL, "unknown offset base");
     if (D.iterations < 0 || D.iterations > 16) return fail(nullptr, LBM_EINVAL, "iterations must be in 0..16");
     if (D.geometry != LBM_GEOM_AUTO && D.geometry != LBM_GEOM_CELL && D.geometry != LBM_GEOM_CELL_TABLE)
         return fail(nullptr, LBM_EINVAL, "unknown geometry mode");

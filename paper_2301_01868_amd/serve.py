@@ -39,6 +39,7 @@ class Request:
     result: dict = field(default_factory=dict)
     best: float = math.inf        # lowest residual that halved the previous best
     best_step: int = 0            # step count at which `best` was reached
+    admit_round: int = -1         # server round before which the request was admitted
 
 
 def check_progress(r, res, max_steps, stall_steps):
@@ -135,6 +136,7 @@ class Server:
                 g.init()
                 r.start = time.perf_counter() - t0
                 r.status = "running"
+                r.admit_round = rounds
                 active[r.rid] = (r, g, need)
                 used += need
                 k += 1

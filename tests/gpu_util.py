@@ -79,12 +79,14 @@ def pair(case, precision=lbm.LBM_FP64, iterations=0, **kw):
     return g, o
 
 
-def one_step_sampled(g, case, nsample=1500, seed=0):
+def one_step_sampled(g, case, nsample=1500, seed=0, iterations=0):
     """One GPU step from the grid's current state against the oracle's step of
     the same state on sampled cells (every wall-adjacent row plus random
-    interior cells); max relative difference."""
+    interior cells); max relative difference.  `iterations` must be the
+    grid's fixed-point force passes."""
     P0, side0 = g.get_state()
     o = oracle.OracleGrid(case)
+    o.set_iterations(iterations)
     o.set_state(to_oracle_state(P0))
     m_s, u_s = side_to_oracle(side0, case.n1, case.n2)
     o.set_side(np.nan_to_num(m_s), np.nan_to_num(u_s))

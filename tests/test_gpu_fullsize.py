@@ -79,8 +79,20 @@ def test_planar_poiseuille_stretched(Ny, tau):
     assert r.bad_cells == 0
     m, U, Ut = g.moments()
     Ut0 = Ut.reshape(case.n1, case.n2, 2)[:, 0]
-    u_peak = case.accel[1] * Ny ** 2 / (8 * G.viscosity(case.q, tau))   # steady parabola's peak
-    assert np.abs(Ut0 - Uto).max() <= 1e-12 * max(np.abs(Uto).max(), u_peak)
+    # FP64 trajectory reading: the 1e-12 gate is per step (the one-step check
+    # below holds 1e-13); over a trajectory the two implementations' rounding
+    # differences (closed-form pair sums against literal index sums) add up
+    # at a size set by the populations, not by how far the flow has developed,
+    # so the bound scales with the flow's velocity scale, the steady
+    # parabola's peak, when the developing flow is still slower (after 1000
+    # steps at tau 0.6 the maximum is 1.0e-3 against a peak of 7.7e-3; the
+    # measured difference, 2.6e-15, is 2.6e-12 of the former and 3.4e-13 of
+    # the latter)
+    u_peak = case.accel[1] * Ny ** 2 / (8 * G.viscosity(case.q, tau))
+    d = np.abs(Ut0 - Uto).max()
+    say("poiseuille", Ny, tau, "fp64 trajectory |dUt| %.2e, max|Ut_oracle| %.2e, peak %.2e"
+        % (d, np.abs(Uto).max(), u_peak))
+    assert d <= 1e-12 * max(np.abs(Uto).max(), u_peak)
     for prec, tol1 in ((lbm.LBM_FP64, 1e-13), (lbm.LBM_FP32, 3e-6)):
         g = lbm.Grid(case, precision=prec)
         g.init()
@@ -161,6 +173,21 @@ def test_ensemble_smallest_full_horizon():
         err = np.abs((col[:, 1] - Uto[:, 1]) * c.meta["centres"] * np.sin(c.meta["dtheta"])).max() / 0.05
         say("instance", k, "Q%d" % c.q, "%dx%d" % (c.n1, c.n2), "u_theta err / U", err)
         assert err <= 1e-5, (k, err)
+
+
+@pytest.mark.parametrize("prec,tol1", [(lbm.LBM_FP64, 1e-13), (lbm.LBM_FP32, 3e-6)], ids=["fp64", "fp32"])
+def test_annulus_256x1024_iterated_force_one_step(prec, tol1):
+    """One fixed-point pass of the implicit force relation on the full-size
+    annulus (the D2Q21 per-row iterating kernel on its unwrapped fast path):
+    one step from the developed GPU state against the oracle's iterated step
+    of that state on sampled cells."""
+    case = G.workload_annulus_couette(256, 1024, tau=0.8)
+    g = lbm.Grid(case, precision=prec, iterations=1)
+    g.init()
+    g.step(200)
+    e1 = _one_step_sampled(g, case, iterations=1)
+    say("annulus 256x1024 iterations 1 prec", prec, "one-step sampled rel err %.2e" % e1)
+    assert e1 <= tol1
 
 
 def _annulus(n1, n2):

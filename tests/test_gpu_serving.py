@@ -12,23 +12,28 @@ pytestmark = pytest.mark.gpu
 
 
 def test_alone_equals_mixed():
+    """Requests admitted into batches that are already running (the budget
+    holds about two and a half of the largest request, so most requests wait
+    for earlier ones to retire) end bitwise as they do alone, after the same
+    number of steps."""
     trace = serve.make_trace(seed=7, rate=400.0, duration=0.05, n_min=16, n_max=32, tol=1e-6)
     say("trace", len(trace), "requests")
     assert len(trace) >= 10
-    srv = serve.Server(hbm_budget=64 << 20, check_every=100)
+    one = max(serve.request_bytes(r.case, lbm.LBM_FP32) for r in trace)
+    srv = serve.Server(hbm_budget=int(2.5 * one), check_every=100)
     info = srv.run(trace, realtime=False)
     s = serve.summarize(trace, info["makespan"])
-    say("mixed", s)
+    say("mixed", s, "admission rounds", [r.admit_round for r in trace])
     assert s["converged"] + s["unstable"] == len(trace)
-    for r in trace[:5]:
+    late = [r for r in trace if r.admit_round > 0]
+    assert len(late) >= 5
+    # the first requests (admitted at round 0) and every late-admitted one
+    for r in trace[:3] + late:
         alone = serve.Request(rid=r.rid, arrival=0.0, case=r.case, tol=r.tol)
         serve.Server(hbm_budget=64 << 20, check_every=100).run([alone], realtime=False)
-        assert alone.status == r.status and alone.steps == r.steps
+        assert alone.status == r.status and alone.steps == r.steps, r.rid
         if r.status == "converged":
-            Ua, Um = alone.result["Ut"], r.result["Ut"]
-            U = max(np.abs(Um).max(), 1e-3)
-            assert np.abs(Ua - Um).max() <= 1e-5 * U
-            assert np.array_equal(Ua, Um)
+            assert np.array_equal(alone.result["Ut"], r.result["Ut"]), r.rid
 
 
 def test_admission_respects_budget():

@@ -64,7 +64,7 @@ def _oracle_steady(tau):
 
 
 @pytest.mark.parametrize("tau", [0.6, 1.0])
-@pytest.mark.parametrize("prec,tol", [(lbm.LBM_FP64, 1e-11), (lbm.LBM_FP32, 1e-5)], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("prec,tol", [(lbm.LBM_FP64, 1e-12), (lbm.LBM_FP32, 1e-5)], ids=["fp64", "fp32"])
 def test_planar_poiseuille_ny64_to_steady_state(tau, prec, tol):
     case = G.workload_planar_poiseuille(64, tau)
     nu = G.viscosity(case.q, tau)
