@@ -283,7 +283,11 @@ void *lbm_stream(lbm_grid *g);
  * graphs and run on the stream of grids[0] (grids on other streams are joined
  * with events before and after).  Every grid must be initialised
  * (LBM_ESTATE otherwise) and appear once (LBM_EINVAL otherwise); n > 0.
- * The batch does not own the grids: destroy the batch before its grids.
+ * The batch does not own the grids: destroy the batch before its grids.  A
+ * grid destroyed while a batch still holds it leaves that batch broken: the
+ * batch drops its references to the grid and its stream, lbm_batch_step,
+ * lbm_batch_step_group, lbm_batch_residuals and lbm_batch_autotune return
+ * LBM_ESTATE, and lbm_batch_destroy only releases it.
  * While it is in a batch a grid must only be stepped through the batch. */
 int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out);
 

@@ -61,6 +61,7 @@ struct lbm_grid {
     bool snap_valid = false;
     int64_t snap_step = 0;
     GraphCache graph[2];
+    std::vector<lbm_batch *> batches;   // batches that hold this grid
     std::string err;
 };
 
@@ -81,6 +82,7 @@ struct lbm_batch {
     std::vector<void *> allocs;
     GraphCache graph;
     int64_t step = 0;
+    bool broken = false;               // a member grid was destroyed first: only destroy is allowed
 };
 
 // ---------------------------------------------------------------------------
@@ -309,10 +311,26 @@ const char *lbm_last_error(const lbm_grid *g)
     return g_last_error.c_str();
 }
 
+// A grid destroyed while a batch still holds it: the batch no longer
+// references the grid or its stream (which may be destroyed below), and every
+// call on it other than lbm_batch_destroy returns LBM_ESTATE.
+static void detach_from_batches(lbm_grid *g)
+{
+    for (lbm_batch *b : g->batches) {
+        b->broken = true;
+        if (b->stream == g->stream) b->stream = nullptr;
+        b->others.erase(std::remove(b->others.begin(), b->others.end(), g->stream), b->others.end());
+        for (auto &m : b->grids)
+            if (m == g) m = nullptr;
+    }
+    g->batches.clear();
+}
+
 void lbm_grid_destroy(lbm_grid *g)
 {
     if (!g) return;
     if (g->stream) (void)hipStreamSynchronize(g->stream);
+    detach_from_batches(g);
     drop_graphs(g);
     auto all = g->allocs;
     for (void *p : all) dfree(g, p);
@@ -1147,10 +1165,20 @@ void lbm_batch_destroy(lbm_batch *b)
 {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (hipStream_t s : b->others) (void)hipStreamSynchronize(s);
     if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
     for (void *p : b->allocs) (void)hipFree(p);
     if (b->ev) (void)hipEventDestroy(b->ev);
+    for (lbm_grid *g : b->grids)
+        if (g) g->batches.erase(std::remove(g->batches.begin(), g->batches.end(), b), g->batches.end());
     delete b;
+}
+
+static int batch_usable(const lbm_batch *b)
+{
+    if (!b) return fail(nullptr, LBM_EINVAL, "null batch");
+    if (b->broken) return fail(nullptr, LBM_ESTATE, "a grid of this batch was destroyed before the batch");
+    return LBM_OK;
 }
 
 // Tile table of a batch group for `wpb` rows per workgroup: the members'
@@ -1255,6 +1283,7 @@ int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_b
         lbm_batch_destroy(b);
         return fail(nullptr, LBM_EDEVICE, "event creation failed");
     }
+    for (lbm_grid *g : b->grids) g->batches.push_back(b);
     *out = b;
     return LBM_OK;
 }
@@ -1293,6 +1322,7 @@ static int batch_launch(lbm_batch *b, int par)
 int lbm_batch_step(lbm_batch *b, int64_t n)
 {
     if (!b || n < 0) return fail(nullptr, LBM_EINVAL, "bad batch step arguments");
+    if (const int u = batch_usable(b)) return u;
     const int GS = 16;
     int64_t left = n;
     {
@@ -1333,6 +1363,7 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
 int lbm_batch_residuals(lbm_batch *b, lbm_resid *out)
 {
     if (!b || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    if (const int u = batch_usable(b)) return u;
     const size_t n = b->grids.size();
     if (!b->d_res) {
         if (hipMalloc((void **)&b->d_res, n * RED_NF * 8) != hipSuccess) return fail(nullptr, LBM_ENOMEM, "allocation failed");
@@ -1378,6 +1409,7 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n)
 {
     if (!b || group < 0 || group >= (int32_t)b->groups.size() || n < 0 || (n & 1))
         return fail(nullptr, LBM_EINVAL, "bad group step arguments (n must be even)");
+    if (const int u = batch_usable(b)) return u;
     const auto &G = b->groups[group];
     StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter);
     for (int64_t k = 0; k < n; ++k)
@@ -1389,7 +1421,7 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n)
 
 int lbm_batch_autotune(lbm_batch *b, int32_t steps)
 {
-    if (!b) return fail(nullptr, LBM_EINVAL, "null batch");
+    if (const int u = batch_usable(b)) return u;
     if (steps < 2) steps = 2;
     steps += steps & 1;                 // even, so every trial keeps the buffer parity
     const int64_t per_trial = 2 + (int64_t)steps;

@@ -165,6 +165,9 @@ class Server:
                     done.append(rid)
             if done:
                 now = time.perf_counter() - t0
+                # the batch goes before the grids it holds (a grid may own its stream)
+                lbm.lbm_batch_destroy(batch)
+                batch = None
                 for rid in done:
                     r, g, need = active.pop(rid)
                     r.finish = now

@@ -252,3 +252,27 @@ def test_checkpoint_blob_resume(prec):
     assert e.value.code == lbm.LBM_EINVAL
     with pytest.raises(lbm.LbmError):
         b.load(b"not a checkpoint" * 4)
+
+
+def test_grid_destroyed_before_its_batch():
+    """A grid destroyed while a batch still holds it (its own stream goes with
+    it) leaves the batch broken: stepping or reducing it returns LBM_ESTATE,
+    destroying it is safe, and the other grid keeps working alone."""
+    cases = [G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, tau=0.8),
+             G.planar_couette(9, G.faces_uniform(8), n2=70, u_wall=0.05, tau=0.8)]
+    grids = [lbm.Grid(c, precision=lbm.LBM_FP32) for c in cases]
+    for g in grids:
+        g.init()
+    b = lbm.lbm_batch_create([g.h for g in grids])
+    lbm.lbm_batch_step(b, 20)
+    grids[0].close()          # the batch runs on this grid's stream
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_batch_step(b, 2)
+    assert e.value.code == lbm.LBM_ESTATE
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_batch_residuals(b, 2)
+    assert e.value.code == lbm.LBM_ESTATE
+    lbm.lbm_batch_destroy(b)
+    grids[1].step(10)
+    assert grids[1].residual().bad_cells == 0
+    assert grids[1].info.step == 30
