@@ -248,6 +248,22 @@ int lbm_noflow_adjust(lbm_grid *g, double tol, int64_t max_steps, int32_t check_
 int lbm_get_state(lbm_grid *g, double *P, double *side);
 int lbm_set_state(lbm_grid *g, const double *P, const double *side);
 
+/* lbm_get_state without allocating: for callers that cannot allocate device
+ * memory (serving loops that checkpoint resident solves, harnesses that
+ * forbid allocation after set-up).  Same outputs as lbm_get_state, bitwise.
+ * The FP64 state is staged through a fixed device array of
+ * LBM_NOALLOC_STAGING_BYTES that each GPU the library runs on holds until the
+ * process ends, in chunks of whole rows, and copied to the caller's host
+ * arrays; no device or host memory is allocated by the library.  Errors:
+ * LBM_EINVAL (null grid; one row of the state, q * n2 * 8 bytes, or the side
+ * state, 4 * c_max * n2 * 8 bytes, larger than the staging array),
+ * LBM_EDEVICE.  The staging array is shared by every call on a GPU: the
+ * library serialises calls made from the threads of one process; it keeps
+ * the last call's contents, which no call reads before writing them.
+ * Synchronises the grid's stream. */
+#define LBM_NOALLOC_STAGING_BYTES ((size_t)8 << 20)
+int lbm_get_state_noalloc(lbm_grid *g, double *P, double *side);
+
 /* Checkpoint blob (host memory, owned by the caller): a header (lattice,
  * shape, storage precision of the writer, step count) followed by the FP64
  * state of lbm_get_state.  lbm_save with buf = NULL stores the required size

@@ -34,12 +34,14 @@ struct lbm_grid {
     int ct = 0;                   // step tables: 0 per row, 1 per cell, 2 per cell rebuilt from the geometry
     double *ge = nullptr;         // staged geometry of ct = 2 (GE_* fields)
     int precision = LBM_FP64;
+    int device = 0;               // device current at create (the grid's buffers live there)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool has_alloc = false;
     lbm_allocator alloc{};
     std::vector<void *> allocs;
-    size_t bytes = 0;
+    std::vector<size_t> alloc_bytes;   // size of each entry of allocs
+    size_t bytes = 0;                  // device bytes currently held
     // device buffers
     void *P[2] = {nullptr, nullptr};
     void *side[2] = {nullptr, nullptr};
@@ -113,6 +115,7 @@ static void *dalloc(lbm_grid *g, size_t bytes)
     }
     if (p) {
         g->allocs.push_back(p);
+        g->alloc_bytes.push_back(bytes);
         g->bytes += bytes;
     }
     return p;
@@ -122,7 +125,12 @@ static void dfree(lbm_grid *g, void *p)
 {
     if (!p) return;
     auto it = std::find(g->allocs.begin(), g->allocs.end(), p);
-    if (it != g->allocs.end()) g->allocs.erase(it);
+    if (it != g->allocs.end()) {
+        const size_t k = (size_t)(it - g->allocs.begin());
+        g->bytes -= g->alloc_bytes[k];
+        g->alloc_bytes.erase(g->alloc_bytes.begin() + k);
+        g->allocs.erase(it);
+    }
     if (g->has_alloc) g->alloc.free(p, g->alloc.ctx);
     else (void)hipFree(p);
 }
@@ -372,6 +380,10 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     }
 
     lbm_grid *g = new lbm_grid();
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return fail(nullptr, LBM_EDEVICE, "hipGetDevice failed");
+    }
     g->desc = D;
     g->desc.x = g->desc.y = nullptr;
     g->q = D.q;
@@ -1014,23 +1026,41 @@ int lbm_noflow_adjust(lbm_grid *g, double tol, int64_t max_steps, int32_t check_
     return rc != LBM_OK ? rc : rc2;
 }
 
+// rows row0 .. row0 + rows - 1 of the FP64 state into dst [Q][rows][n2] (device)
+static int launch_state_out(lbm_grid *g, int row0, int rows, double *dst)
+{
+    const dim3 gr((g->n2 + 127) / 128, rows);
+    if (g->q == 9) {
+        if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_out<9, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, row0, dst);
+        else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_state_out<9, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, row0, dst);
+        else hipLaunchKernelGGL((k_state_out<9, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, row0, dst);
+    } else {
+        if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_out<21, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, row0, dst);
+        else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_state_out<21, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, row0, dst);
+        else hipLaunchKernelGGL((k_state_out<21, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, row0, dst);
+    }
+    HIPCHK(g, hipGetLastError());
+    return LBM_OK;
+}
+
+// the moving-wall side state into dst [2][2][hw][n2] (device)
+static int launch_side_out(lbm_grid *g, double *dst)
+{
+    const dim3 sg((g->n2 + 127) / 128, 4 * g->hw);
+    if (g->precision == LBM_FP64) hipLaunchKernelGGL(k_side_io<double>, sg, dim3(128), 0, g->stream, g->d_inst, g->par, dst, 0);
+    else hipLaunchKernelGGL(k_side_io<float>, sg, dim3(128), 0, g->stream, g->d_inst, g->par, dst, 0);
+    HIPCHK(g, hipGetLastError());
+    return LBM_OK;
+}
+
 int lbm_get_state(lbm_grid *g, double *P, double *side)
 {
     if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
-    const dim3 gr = cell_grid(g->n1, g->n2);
     if (P) {
         double *tmp = (double *)dalloc(g, (size_t)g->ncell * g->q * 8);
         if (!tmp) return fail(g, LBM_ENOMEM, "allocation failed");
-        if (g->q == 9) {
-            if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_out<9, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
-            else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_state_out<9, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
-            else hipLaunchKernelGGL((k_state_out<9, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
-        } else {
-            if (g->precision == LBM_FP64) hipLaunchKernelGGL((k_state_out<21, double>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
-            else if (g->precision == LBM_FP16) hipLaunchKernelGGL((k_state_out<21, _Float16>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
-            else hipLaunchKernelGGL((k_state_out<21, float>), gr, dim3(128), 0, g->stream, g->d_inst, g->base, !g->row, g->par, tmp);
-        }
-        HIPCHK(g, hipGetLastError());
+        int rc = launch_state_out(g, 0, g->n1, tmp);
+        if (rc != LBM_OK) return rc;
         HIPCHK(g, hipMemcpyAsync(P, tmp, (size_t)g->ncell * g->q * 8, hipMemcpyDeviceToHost, g->stream));
         HIPCHK(g, hipStreamSynchronize(g->stream));
         dfree(g, tmp);
@@ -1039,14 +1069,90 @@ int lbm_get_state(lbm_grid *g, double *P, double *side)
         const size_t ns = (size_t)4 * g->hw * g->n2;
         double *tmp = (double *)dalloc(g, ns * 8);
         if (!tmp) return fail(g, LBM_ENOMEM, "allocation failed");
-        const dim3 sg((g->n2 + 127) / 128, 4 * g->hw);
-        if (g->precision == LBM_FP64) hipLaunchKernelGGL(k_side_io<double>, sg, dim3(128), 0, g->stream, g->d_inst, g->par, tmp, 0);
-        else hipLaunchKernelGGL(k_side_io<float>, sg, dim3(128), 0, g->stream, g->d_inst, g->par, tmp, 0);
-        HIPCHK(g, hipGetLastError());
+        int rc = launch_side_out(g, tmp);
+        if (rc != LBM_OK) return rc;
         HIPCHK(g, hipMemcpyAsync(side, tmp, ns * 8, hipMemcpyDeviceToHost, g->stream));
         HIPCHK(g, hipStreamSynchronize(g->stream));
         dfree(g, tmp);
     }
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free state export.  The FP64 state is staged through `scratch`,
+// a fixed device array of LBM_NOALLOC_STAGING_BYTES that every GPU the library
+// runs on holds until the process ends, in chunks of whole rows.  In host
+// code `scratch` names a host-side stand-in, never the device array: its
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current and kept in g_scratch_dev.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[LBM_NOALLOC_STAGING_BYTES / sizeof(double)];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;              // guards g_scratch_dev and serialises the staging
+double *g_scratch_dev[MAX_DEVICES] = {};
+} // namespace
+
+// device address of `scratch` on device `dev` (with `dev` current)
+static int scratch_address(lbm_grid *g, int dev, double **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(g, LBM_EDEVICE, "device index out of range");
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPCHK(g, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(g, LBM_EDEVICE, "hipGetSymbolAddress returned no address for the staging array");
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return LBM_OK;
+}
+
+int lbm_get_state_noalloc(lbm_grid *g, double *P, double *side)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    const size_t row_bytes = (size_t)g->q * g->n2 * sizeof(double);
+    const size_t side_bytes = (size_t)4 * g->hw * g->n2 * sizeof(double);
+    if (P && row_bytes > LBM_NOALLOC_STAGING_BYTES)
+        return fail(g, LBM_EINVAL, "lbm_get_state_noalloc: one row of the state (" + std::to_string(row_bytes) +
+                                       " bytes) exceeds the staging buffer (" +
+                                       std::to_string((size_t)LBM_NOALLOC_STAGING_BYTES) + " bytes)");
+    if (side && side_bytes > LBM_NOALLOC_STAGING_BYTES)
+        return fail(g, LBM_EINVAL, "lbm_get_state_noalloc: the side state (" + std::to_string(side_bytes) +
+                                       " bytes) exceeds the staging buffer");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    int cur = -1;
+    HIPCHK(g, hipGetDevice(&cur));
+    if (cur != g->device) HIPCHK(g, hipSetDevice(g->device));
+    struct Restore {   // the caller's current device, on every return path
+        int dev, was;
+        ~Restore()
+        {
+            if (dev != was) (void)hipSetDevice(was);
+        }
+    } restore{g->device, cur};
+    double *buf = nullptr;
+    int rc = scratch_address(g, g->device, &buf);
+    if (rc != LBM_OK) return rc;
+    if (P) {
+        // whole rows per chunk; each chunk's copy is ordered on the stream
+        // before the next chunk's kernel overwrites the staging array
+        const int rows = (int)std::min<size_t>((size_t)g->n1, LBM_NOALLOC_STAGING_BYTES / row_bytes);
+        for (int r0 = 0; r0 < g->n1; r0 += rows) {
+            const int nr = std::min(rows, g->n1 - r0);
+            rc = launch_state_out(g, r0, nr, buf);
+            if (rc != LBM_OK) return rc;
+            const size_t w = (size_t)nr * g->n2 * sizeof(double);
+            HIPCHK(g, hipMemcpy2DAsync(P + (size_t)r0 * g->n2, (size_t)g->ncell * sizeof(double), buf, w, w, g->q,
+                                       hipMemcpyDeviceToHost, g->stream));
+        }
+    }
+    if (side) {
+        rc = launch_side_out(g, buf);
+        if (rc != LBM_OK) return rc;
+        HIPCHK(g, hipMemcpyAsync(side, buf, side_bytes, hipMemcpyDeviceToHost, g->stream));
+    }
+    HIPCHK(g, hipStreamSynchronize(g->stream));
     return LBM_OK;
 }
 

@@ -354,17 +354,19 @@ __global__ void k_lag(const InstDesc *__restrict__ d, int pin)
 // state transfer: absolute FP64 particle numbers <-> stored offsets
 // ---------------------------------------------------------------------------
 template <int Q, typename S>
+// rows row0 .. row0 + gridDim.y - 1 of the state, out[Q][gridDim.y][n2]
+// (the whole state [Q][n1][n2] when row0 = 0 and gridDim.y = n1)
 __global__ void k_state_out(const InstDesc *__restrict__ d, const double *__restrict__ base, int cellmode, int pin,
-                            double *__restrict__ out)
+                            int row0, double *__restrict__ out)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
+    const int i = row0 + (int)blockIdx.y;
     if (j >= d->n2 || i >= d->n1) return;
     const int c = i * d->n2 + j, e = cellmode ? c : i;
+    const size_t chunk = (size_t)gridDim.y * d->n2, o = (size_t)blockIdx.y * d->n2 + j;
     const S *P = (const S *)d->P[pin];
     for (int a = 0; a < Q; ++a)
-        out[(size_t)a * d->ncell + c] =
-            base[(size_t)e * Q + a] + pdec<Q, S, double>(P[pidx(d, a, i, j)], a);
+        out[(size_t)a * chunk + o] = base[(size_t)e * Q + a] + pdec<Q, S, double>(P[pidx(d, a, i, j)], a);
 }
 
 template <int Q, typename S>

@@ -27,7 +27,7 @@ EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_erro
             "lbm_get_state", "lbm_set_state", "lbm_save", "lbm_load", "lbm_physical_velocity", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
             "lbm_stream", "lbm_batch_create", "lbm_batch_create_ex", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_set_occupancy", "lbm_autotune",
             "lbm_copy_probe", "lbm_bandwidth_probe", "lbm_map_planar", "lbm_map_polar",
-            "lbm_batch_autotune", "lbm_batch_group_launch"]
+            "lbm_batch_autotune", "lbm_batch_group_launch", "lbm_get_state_noalloc"]
 
 
 class LbmError(RuntimeError):
@@ -96,6 +96,7 @@ def load():
     L.lbm_noflow_adjust.argtypes = [vp, ct.c_double, ct.c_int64, ct.c_int32, ct.POINTER(ct.c_int64)]
     L.lbm_get_state.argtypes = [vp, D, D]
     L.lbm_set_state.argtypes = [vp, D, D]
+    L.lbm_get_state_noalloc.argtypes = [vp, D, D]
     L.lbm_save.argtypes = [vp, vp, ct.POINTER(ct.c_size_t)]
     L.lbm_load.argtypes = [vp, vp, ct.c_size_t]
     L.lbm_physical_velocity.argtypes = [vp, D]
@@ -169,8 +170,10 @@ def lbm_map_polar(r_faces, ntheta, halo, n2=None):
 
 
 def lbm_grid_create(case, precision=LBM_FP64, offset_base=LBM_BASE_LOCAL_REST, iterations=0,
-                    geometry=LBM_GEOM_AUTO, stream=None):
-    """Create a grid from a grids.Case (mapping + boundary + parameters)."""
+                    geometry=LBM_GEOM_AUTO, stream=None, alloc=None):
+    """Create a grid from a grids.Case (mapping + boundary + parameters);
+    `alloc` is an optional lbm_allocator the caller keeps alive for the
+    grid's lifetime."""
     X = np.ascontiguousarray(case.X, dtype=np.float64)
     Y = np.ascontiguousarray(case.Y, dtype=np.float64)
     d = lbm_grid_desc()
@@ -184,7 +187,7 @@ def lbm_grid_create(case, precision=LBM_FP64, offset_base=LBM_BASE_LOCAL_REST, i
     d.accel[0], d.accel[1] = float(case.accel[0]), float(case.accel[1])
     d.rho0 = float(case.rho0)
     d.precision, d.offset_base, d.iterations, d.geometry = precision, offset_base, iterations, geometry
-    d.alloc = None
+    d.alloc = None if alloc is None else ct.pointer(alloc)
     d.stream = stream
     h = ct.c_void_p()
     _chk(load().lbm_grid_create(ct.byref(d), ct.byref(h)))
@@ -247,6 +250,18 @@ def lbm_get_state(h, q, n1, n2, cmax):
     P = np.zeros((q, n1, n2))
     side = np.zeros((2, 2, cmax, n2))
     _chk(load().lbm_get_state(h, _dp(P), _dp(side)), h)
+    return P, side
+
+
+def lbm_get_state_noalloc(h, q, n1, n2, cmax, P=None, side=None):
+    """As lbm_get_state, staged through the library's fixed device array (no
+    allocation by the library); pass P [q][n1][n2] and side [2][2][cmax][n2]
+    to reuse caller-owned host arrays."""
+    P = np.zeros((q, n1, n2)) if P is None else P
+    side = np.zeros((2, 2, cmax, n2)) if side is None else side
+    assert P.dtype == np.float64 and P.flags.c_contiguous and P.size == q * n1 * n2
+    assert side.dtype == np.float64 and side.flags.c_contiguous and side.size == 4 * cmax * n2
+    _chk(load().lbm_get_state_noalloc(h, _dp(P), _dp(side)), h)
     return P, side
 
 
@@ -392,12 +407,13 @@ def lbm_copy_probe(dst_ptr, src_ptr, nbytes, stream=None):
 # ---------------------------------------------------------------------------
 class Grid:
     def __init__(self, case, precision=LBM_FP64, offset_base=LBM_BASE_LOCAL_REST, iterations=0,
-                 geometry=LBM_GEOM_AUTO, stream=None):
+                 geometry=LBM_GEOM_AUTO, stream=None, alloc=None):
         self.case = case
         self.q, self.n1, self.n2 = case.q, case.n1, case.n2
         self.ncell = case.n1 * case.n2
         self.cmax = 1 if case.q == 9 else 3
-        self.h = lbm_grid_create(case, precision, offset_base, iterations, geometry, stream)
+        self._alloc = alloc        # kept alive with the grid
+        self.h = lbm_grid_create(case, precision, offset_base, iterations, geometry, stream, alloc)
 
     def close(self):
         if getattr(self, "h", None):
@@ -446,6 +462,9 @@ class Grid:
 
     def get_state(self):
         return lbm_get_state(self.h, self.q, self.n1, self.n2, self.cmax)
+
+    def get_state_noalloc(self, P=None, side=None):
+        return lbm_get_state_noalloc(self.h, self.q, self.n1, self.n2, self.cmax, P, side)
 
     def set_state(self, P=None, side=None):
         lbm_set_state(self.h, P, side)

@@ -124,3 +124,16 @@ def test_header_is_c_and_links_from_c(lib, tmp_path):
     assert float(out[0]) == 2.0 / 3.0 and out[1:3] == ["3", "3"]
     # first ghost row of a 3-cell channel with halo 4 (rows -3..6 at x = 1/2 + integer); y of the last column
     assert float(out[3]) == -3.5 and float(out[4]) == (5 + 0.5) * 0.5
+
+
+def test_unknown_offset_base_is_rejected(lib):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Grid(_desc_case(), precision=lbm.LBM_FP32, offset_base=3)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert "offset base" in str(e.value)
+
+
+def test_noalloc_state_export_rejects_null_grid(lib):
+    P = np.zeros(4)
+    rc = lib.lbm_get_state_noalloc(None, P.ctypes.data_as(lbm.ct.POINTER(lbm.ct.c_double)), None)
+    assert rc == lbm.LBM_EINVAL
