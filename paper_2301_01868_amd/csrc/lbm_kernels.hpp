@@ -570,50 +570,26 @@ struct TabSel<Q, T, 2> {
 };
 
 // ---------------------------------------------------------------------------
-// the fused step (pull + moments + force + equilibrium + flux correction +
-// curvilinear correction + BGK + store), one cell per lane, one row segment of
-// 64 columns per wave; MOM = true computes and writes the moments instead of
-// colliding.  CT: 0 per-row tables, 1 per-cell tables, 2 per-cell fields
-// rebuilt from the staged geometry.
+// Pieces of the fused step (pull + moments + force + equilibrium + flux
+// correction + curvilinear correction + BGK + store), one cell per lane.
+// CT: 0 per-row tables, 1 per-cell tables, 2 per-cell fields rebuilt from
+// the staged geometry.
 // ---------------------------------------------------------------------------
-template <int Q, typename T, typename S, int CT, bool MOM, bool ITER>
-__device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, const int4 tl, int par)
+
+// Pulled populations N_a(i, j) of Eq. (adv) with the boundary sources of
+// App. B, read from the post-collision field in HBM and moved to the cell's
+// compute base.  j0 is the first column of the wave's 64.
+template <int Q, typename T, typename S, int CT, typename TBT>
+__device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const TBT &tb, int i, int j, int j0, int pin,
+                                          T (&n)[Q])
 {
     constexpr int CM = cmax<Q>();
-    constexpr int NP = npair<Q>();
     constexpr double T0d = lattice_T0<Q>();
     using TB = Tab<Q>;
-
-    const InstDesc *__restrict__ d = insts + tl.x;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int i = tl.y + wave;
     const int n1 = d->n1, n2 = d->n2;
-    const double *geo_lds = nullptr;
-    if constexpr (CT == 2) {
-        if (tl.y >= n1) return;   // padding tile (the whole workgroup)
-        geo_lds = stage_geometry<Q, T>(d, tl, wave);
-    }
-    if (i >= n1) return;
-    const int j0 = tl.z;
-    const int j = j0 + (int)(threadIdx.x & 63);
-    if (j >= n2) return;
-
     const int pitch = d->pitch, hw = d->hw;
     const long long plane = d->plane;
-    const int pin = (par ^ d->par0) & 1;
     const int bclo = d->bc_lo, bchi = d->bc_hi, per1 = d->periodic1;
-
-    typename TabSel<Q, T, CT>::type tb;
-    if constexpr (CT == 2) {
-        tb.setup(d, geo_lds, wave, j - j0, i, j);
-    } else if constexpr (CT == 1) {
-        tb.p = (const T *)d->tab + (size_t)i * n2 + j;
-        tb.s = d->ncell;
-    } else {
-        tb.p = (const T *)d->tab + (size_t)i * TB::STRIDE;
-        tb.s = 1;
-    }
-
     constexpr uint32_t ES = sizeof(S);
     const uint32_t sa_b = (uint32_t)d->sa * ES, sr_b = (uint32_t)d->sr * ES, sb_b = (uint32_t)d->sb * ES;
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(d->P[pin], (uint32_t)(plane * Q) * ES);
@@ -622,8 +598,6 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
     // byte offset of the wave's own cells inside a row
     const uint32_t jb = (uint32_t)(j >> bs) * sb_b + (uint32_t)(j & bm) * ES;
 
-    // ---- pull streaming with boundary sources ----
-    T n[Q], s[Q];
     const bool interior = (i >= CM && i < n1 - CM);
     const bool nowrap = (j0 >= CM) && (j0 + 63 + CM < n2);
     if (interior && nowrap) {
@@ -703,14 +677,26 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
         }
     }
     phase_fence<CT>();
-    // lagged own-cell force sums sum_a A+^i_a s_a(q, t-1), formed when the
-    // previous step produced N'(q, t-1)
-    constexpr uint32_t ET = sizeof(T);
-    const uint32_t lag_bytes = 2 * (uint32_t)plane * ET, lsa_b = (uint32_t)d->lsa * ET;
-    const __amdgpu_buffer_rsrc_t rlag = make_rsrc(d->lag[pin], lag_bytes);
-    const uint32_t jt = (uint32_t)j * ET, rowt = (uint32_t)i * (uint32_t)d->lsr * ET;
-    const T Lo1 = bload<T, T>(rlag, jt, rowt);
-    const T Lo2 = bload<T, T>(rlag, jt, lsa_b + rowt);
+}
+
+// what the store and the moments pass need besides the post-collision values
+template <typename T>
+struct CellOut {
+    T m, dm, U1, U2, Ut1, Ut2, JF1, JF2;
+};
+
+// Moments, lagged (or iterated) force, physical velocity, equilibrium,
+// momentum-flux correction, curvilinear correction and BGK relaxation of one
+// cell: n are the pulled populations, Lo the lagged own-cell force sums
+// sum_a A+^i_a s_a(q, t - 1) (Eq. compo-constr), s the post-collision values,
+// all relative to the cell's compute base.  MOM stops after the force.
+template <int Q, typename T, int CT, bool MOM, bool ITER, typename TBT>
+__device__ __forceinline__ void collide_cell(const InstDesc *__restrict__ d, const TBT &tb, const T (&n)[Q], T Lo1,
+                                             T Lo2, T (&s)[Q], CellOut<T> &o)
+{
+    constexpr int NP = npair<Q>();
+    constexpr double T0d = lattice_T0<Q>();
+    using TB = Tab<Q>;
 
     // ---- moments (in +-c pairs) ----
     T dm = n[0], mU1 = 0, mU2 = 0;
@@ -823,17 +809,31 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
         phase_fence<CT>();
         if (it >= iters) break;
     }
+    o.m = m;
+    o.dm = dm;
+    o.U1 = U1;
+    o.U2 = U2;
+    o.Ut1 = Ut1;
+    o.Ut2 = Ut2;
+    o.JF1 = JF1;
+    o.JF2 = JF2;
+}
 
-    if constexpr (!MOM && sizeof(T) == 4 && sizeof(S) == 4) {
-        // In exact arithmetic the update keeps sum_a N_a and changes
-        // sum_a c_a N_a by exactly J F (with fourth-order isotropy the
-        // equilibrium carries momentum m U, the correction dN carries J F).
-        // Single-precision products of population size miss these moments by
-        // ~1e-7 of the local momentum, the same miss every step once the flow
-        // is steady, which acts as a spurious body force integrated over the
-        // slowest viscous time.  The miss is measured on the small differences
-        // N' - N and removed along w_a (1, c_a / T0), which changes no other
-        // moment of the update.  (FP16 storage rounds far above this level.)
+// FP32 storage: the update's mass and momentum projected onto their values in
+// exact arithmetic.  In exact arithmetic the update keeps sum_a N_a and
+// changes sum_a c_a N_a by exactly J F (with fourth-order isotropy the
+// equilibrium carries momentum m U, the correction dN carries J F).
+// Single-precision products of population size miss these moments by ~1e-7 of
+// the local momentum, the same miss every step once the flow is steady, which
+// acts as a spurious body force integrated over the slowest viscous time.  The
+// miss is measured on the small differences N' - N and removed along
+// w_a (1, c_a / T0), which changes no other moment of the update.  (FP16
+// storage rounds far above this level.)
+template <int Q, typename T, typename S>
+__device__ __forceinline__ void project_update(const T (&n)[Q], T (&s)[Q], T JF1, T JF2)
+{
+    if constexpr (sizeof(T) == 4 && sizeof(S) == 4) {
+        constexpr double T0d = lattice_T0<Q>();
         T r0 = 0, r1 = -JF1, r2 = -JF2;
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
@@ -851,6 +851,138 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             s[a] -= (T)weight<Q>(a) * corr;
         }
     }
+}
+
+// Store the post-collision values of cell (i, j) (moved to the storage base
+// and encoded), with LAGW the lagged force sums the next step of the
+// lag-buffer kernels reads, and the moving walls' side state: m and Ut^2 of
+// the rows a wall pulls from (App. B.3).
+template <int Q, typename T, typename S, int CT, bool LAGW, typename TBT>
+__device__ __forceinline__ void store_cell(const InstDesc *__restrict__ d, const TBT &tb, int i, int j, int pin,
+                                           const T (&s)[Q], const CellOut<T> &o)
+{
+    using TB = Tab<Q>;
+    constexpr uint32_t ES = sizeof(S);
+    const long long plane = d->plane;
+    const uint32_t sa_b = (uint32_t)d->sa * ES, sr_b = (uint32_t)d->sr * ES, sb_b = (uint32_t)d->sb * ES;
+    const uint32_t jb = (uint32_t)(j >> d->bs) * sb_b + (uint32_t)(j & d->bm) * ES;
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(d->P[pin ^ 1], (uint32_t)(plane * Q) * ES);
+    T Lx1 = 0, Lx2 = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const T st = s[a] + tb(TB::SB(a));                                  // storage base
+        pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + (uint32_t)i * sr_b, a, st);
+        if constexpr (LAGW) {
+            const T v = pdec<Q, S, T>(penc<Q, S, T>(st, a), a) - tb(TB::SB(a));  // as stored, compute base
+            if (a > 0) {
+                Lx1 += tb(TB::A1(a)) * v;
+                Lx2 += tb(TB::A2(a)) * v;
+            }
+        }
+        sgroup<CT>();
+    }
+    if constexpr (LAGW) {
+        constexpr uint32_t ET = sizeof(T);
+        const uint32_t lag_bytes = 2 * (uint32_t)plane * ET, lsa_b = (uint32_t)d->lsa * ET;
+        const uint32_t jt = (uint32_t)j * ET, rowt = (uint32_t)i * (uint32_t)d->lsr * ET;
+        const __amdgpu_buffer_rsrc_t rlago = make_rsrc(d->lag[pin ^ 1], lag_bytes);
+        bstore<T, T>(rlago, jt, rowt, Lx1);
+        bstore<T, T>(rlago, jt, lsa_b + rowt, Lx2);
+    }
+    const int n1 = d->n1, hw = d->hw, pitch = d->pitch;
+    T *side_out = (T *)d->side[pin ^ 1];
+    if (d->bc_lo == BC_MOVING && i < hw) {
+        side_out[((size_t)0 * hw + i) * pitch + j] = o.m;
+        side_out[((size_t)1 * hw + i) * pitch + j] = o.Ut2;
+    }
+    if (d->bc_hi == BC_MOVING && i >= n1 - hw) {
+        const int k = n1 - 1 - i;
+        side_out[((size_t)2 * hw + k) * pitch + j] = o.m;
+        side_out[((size_t)3 * hw + k) * pitch + j] = o.Ut2;
+    }
+}
+
+// Lagged own-cell force sums sum_a A+^i_a s_a(q, t - 1) from the own cell's
+// stored post-collision values (the sums the lag-buffer kernels store, formed
+// in the same order, so bitwise the same)
+template <int Q, typename T, typename S, typename TBT>
+__device__ __forceinline__ void own_lag_global(const InstDesc *__restrict__ d, const TBT &tb, int i, int j, int pin,
+                                               T &Lo1, T &Lo2)
+{
+    using TB = Tab<Q>;
+    constexpr uint32_t ES = sizeof(S);
+    const uint32_t sa_b = (uint32_t)d->sa * ES, sr_b = (uint32_t)d->sr * ES, sb_b = (uint32_t)d->sb * ES;
+    const uint32_t jb = (uint32_t)(j >> d->bs) * sb_b + (uint32_t)(j & d->bm) * ES;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(d->P[pin], (uint32_t)(d->plane * Q) * ES);
+    Lo1 = 0;
+    Lo2 = 0;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        const T v = pload<Q, S, T>(rin, jb, (uint32_t)a * sa_b + (uint32_t)i * sr_b, a) - tb(TB::SB(a));
+        Lo1 += tb(TB::A1(a)) * v;
+        Lo2 += tb(TB::A2(a)) * v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The step of the lag-buffer kernels: one row segment of 64 columns per wave;
+// the lagged force sums of the own cell are read from, and the next ones
+// written to, a per-cell buffer.  MOM = true computes and writes the moments
+// instead of colliding (for per-row tables it forms the lagged sums from the
+// own cell's stored values, which serves grids stepped by either kernel).
+// ---------------------------------------------------------------------------
+template <int Q, typename T, typename S, int CT, bool MOM, bool ITER>
+__device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, const int4 tl, int par)
+{
+    using TB = Tab<Q>;
+
+    const InstDesc *__restrict__ d = insts + tl.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i = tl.y + wave;
+    const int n1 = d->n1, n2 = d->n2;
+    const double *geo_lds = nullptr;
+    if constexpr (CT == 2) {
+        if (tl.y >= n1) return;   // padding tile (the whole workgroup)
+        geo_lds = stage_geometry<Q, T>(d, tl, wave);
+    }
+    if (i >= n1) return;
+    const int j0 = tl.z;
+    const int j = j0 + (int)(threadIdx.x & 63);
+    if (j >= n2) return;
+    const int pin = (par ^ d->par0) & 1;
+
+    typename TabSel<Q, T, CT>::type tb;
+    if constexpr (CT == 2) {
+        tb.setup(d, geo_lds, wave, j - j0, i, j);
+    } else if constexpr (CT == 1) {
+        tb.p = (const T *)d->tab + (size_t)i * n2 + j;
+        tb.s = d->ncell;
+    } else {
+        tb.p = (const T *)d->tab + (size_t)i * TB::STRIDE;
+        tb.s = 1;
+    }
+
+    T n[Q], s[Q];
+    pull_cell<Q, T, S, CT>(d, tb, i, j, j0, pin, n);
+
+    T Lo1, Lo2;
+    if constexpr (MOM && CT == 0) {
+        own_lag_global<Q, T, S>(d, tb, i, j, pin, Lo1, Lo2);
+    } else {
+        // lagged own-cell force sums, formed when the previous step produced
+        // N'(q, t-1)
+        constexpr uint32_t ET = sizeof(T);
+        const uint32_t lag_bytes = 2 * (uint32_t)d->plane * ET, lsa_b = (uint32_t)d->lsa * ET;
+        const __amdgpu_buffer_rsrc_t rlag = make_rsrc(d->lag[pin], lag_bytes);
+        const uint32_t jt = (uint32_t)j * ET, rowt = (uint32_t)i * (uint32_t)d->lsr * ET;
+        Lo1 = bload<T, T>(rlag, jt, rowt);
+        Lo2 = bload<T, T>(rlag, jt, lsa_b + rowt);
+    }
+
+    CellOut<T> o;
+    collide_cell<Q, T, CT, MOM, ITER>(d, tb, n, Lo1, Lo2, s, o);
+
+    if constexpr (!MOM) project_update<Q, T, S>(n, s, o.JF1, o.JF2);
 
     phase_fence<CT>();
     if constexpr (MOM) {
@@ -858,39 +990,13 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
         const int e = CT ? c : i;
         double *mo = d->mom;
         const size_t nc = (size_t)d->ncell;
-        mo[c] = d->mB64[e] + (double)dm;
-        mo[nc + c] = (double)U1;
-        mo[2 * nc + c] = (double)U2;
-        mo[3 * nc + c] = (double)Ut1;
-        mo[4 * nc + c] = (double)Ut2;
+        mo[c] = d->mB64[e] + (double)o.dm;
+        mo[nc + c] = (double)o.U1;
+        mo[2 * nc + c] = (double)o.U2;
+        mo[3 * nc + c] = (double)o.Ut1;
+        mo[4 * nc + c] = (double)o.Ut2;
     } else {
-        const __amdgpu_buffer_rsrc_t rout = make_rsrc(d->P[pin ^ 1], (uint32_t)(plane * Q) * ES);
-        T Lx1 = 0, Lx2 = 0;
-#pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            const T st = s[a] + tb(TB::SB(a));                                  // storage base
-            const T v = pdec<Q, S, T>(penc<Q, S, T>(st, a), a) - tb(TB::SB(a));  // as stored, compute base
-            pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + (uint32_t)i * sr_b, a, st);
-            if (a > 0) {
-                Lx1 += tb(TB::A1(a)) * v;
-                Lx2 += tb(TB::A2(a)) * v;
-            }
-            sgroup<CT>();
-        }
-        const __amdgpu_buffer_rsrc_t rlago = make_rsrc(d->lag[pin ^ 1], lag_bytes);
-        bstore<T, T>(rlago, jt, rowt, Lx1);
-        bstore<T, T>(rlago, jt, lsa_b + rowt, Lx2);
-        // side state of the moving walls: m and Ut^2 of the rows a wall pulls from
-        T *side_out = (T *)d->side[pin ^ 1];
-        if (bclo == BC_MOVING && i < hw) {
-            side_out[((size_t)0 * hw + i) * pitch + j] = m;
-            side_out[((size_t)1 * hw + i) * pitch + j] = Ut2;
-        }
-        if (bchi == BC_MOVING && i >= n1 - hw) {
-            const int k = n1 - 1 - i;
-            side_out[((size_t)2 * hw + k) * pitch + j] = m;
-            side_out[((size_t)3 * hw + k) * pitch + j] = Ut2;
-        }
+        store_cell<Q, T, S, CT, true>(d, tb, i, j, pin, s, o);
     }
 }
 

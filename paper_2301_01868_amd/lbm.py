@@ -3,6 +3,11 @@
 Every function has the ABI's name and forwards to ``liblbm.so``; nothing here
 computes any step of the method.  Loading fails loudly when the library has
 not been built (``python -m paper_2301_01868_amd.build``).
+
+PyTorch ships its own HIP runtime with the same soname (libamdhip64.so.7) as
+the ROCm one the library links; a process uses the first one loaded for both
+only if torch is imported first.  Import torch before the first ``load()``
+when passing torch streams or torch memory to the library.
 """
 from __future__ import annotations
 

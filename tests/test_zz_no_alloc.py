@@ -3,6 +3,7 @@ MI355X; collected last): bitwise the same state and side state on two calls in a
 second on a smaller grid; no allocation through the grid's allocator during
 the call; rows wider than the staging array rejected."""
 import ctypes as ct
+import os
 
 import numpy as np
 import pytest
@@ -18,11 +19,14 @@ FREE = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
 
 
 class CountingAllocator:
-    """Device memory from PyTorch's caching allocator, with call counts."""
+    """Device memory from hipMalloc / hipFree of the HIP runtime the library
+    itself is bound to (called through ctypes), with call counts."""
 
     def __init__(self):
-        import torch
-        self.torch = torch
+        lbm.load()
+        self.hip = ct.CDLL("libamdhip64.so.7", mode=os.RTLD_NOLOAD | os.RTLD_GLOBAL)
+        self.hip.hipMalloc.argtypes = [ct.POINTER(ct.c_void_p), ct.c_size_t]
+        self.hip.hipFree.argtypes = [ct.c_void_p]
         self.allocs = 0
         self.frees = 0
         self._a = ALLOC(self._alloc)
@@ -31,11 +35,12 @@ class CountingAllocator:
 
     def _alloc(self, nbytes, ctx):
         self.allocs += 1
-        return self.torch.cuda.caching_allocator_alloc(int(nbytes))
+        p = ct.c_void_p()
+        return p.value if self.hip.hipMalloc(ct.byref(p), nbytes) == 0 else None
 
     def _free(self, ptr, ctx):
         self.frees += 1
-        self.torch.cuda.caching_allocator_delete(ptr)
+        self.hip.hipFree(ptr)
 
 
 def _export_both(g, alloc):
