@@ -6,3 +6,4 @@ It shares no code with the HIP library.
 """
 from .oracle import OracleGrid, lattice, feq, build, lib_path, max_threads  # noqa: F401
 from . import exact  # noqa: F401
+from . import oracle3d  # noqa: F401

@@ -26,8 +26,8 @@
  *     (App. A): the printed 7/432 and 7/1620 do not sum to one; 1/432, 1/1620;
  *   - velocity numbering is inferred from the App. B index tables;
  *   - wall sources: the source node x - c_alpha beyond a wall is replaced by
- *     its mirror image across the wall plane (App. B.2, "extended through the
- *     boundaries using symmetry"); no-slip takes the bounce-back direction
+ *     its mirror image across the wall plane (App. B.2 continues the source
+ *     through the wall by symmetry without giving the rule); no-slip takes the bounce-back direction
  *     alpha*, a moving wall the specular direction alpha-hat plus
  *     2 w_alpha m(z) c^2_alpha (U0^2 - Utilde^2(z)) / T0 with m(z) the
  *     number of particles in the image cell z from its last collision, only

@@ -25,7 +25,9 @@ def lib_path() -> str:
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no FP contraction, OpenMP)."""
+    """Compile the oracles (2D and 3D) with gcc (-O2, no FP contraction, OpenMP)."""
+    from . import oracle3d
+    oracle3d.build(force)
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
