@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "lbm_lib.hip")
+SRC = [os.path.join(HERE, "csrc", "lbm_lib.hip"), os.path.join(HERE, "csrc", "lbm3d_lib.hip")]
 OUT = os.path.join(HERE, "liblbm.so")
 
 HIPCC_FLAGS = [
@@ -21,7 +21,7 @@ HIPCC_FLAGS = [
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", tmp, SRC]
+           "-o", tmp, *SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

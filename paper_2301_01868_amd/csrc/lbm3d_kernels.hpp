@@ -1,0 +1,525 @@
+// Device code of the three-dimensional step (arXiv:2301.01868, Sec. 2 for
+// i = 1, 2, 3; boundaries of App. B on the q1 sides, q2 and q3 periodic).
+//
+// FP64 populations in particle numbers N = J f, in which J cancels from the
+// update:
+//   m = sum N,  m U^i = sum c^i N                                   (Eqs. moments, vcomp)
+//   J F^i = -1/2 sum_a A+^i_a [N'_a(q, t-1) + N_{-a}(q, t)] + m a^i  (Eq. compo-constr,
+//            with A-^i_a = -A+^i_{-a} and the paper's one-step lag)
+//   Ut = U + J F / (2 m)
+//   J f^eq_a = m phi_a                                              (Eq. equilibrium)
+//   J dPi^ij = -1/2 (1 - 1/(2 tau)) sum_a c^i_a (A+^j_a + A+^j_{-a}) m phi_a   (Eq. delta-flux)
+//   dN_a = w_a [c.JF / T0 + (c^j c^k / T0 - delta^jk) J dPi^jk / T0]          (Eq. deltaN)
+//   N'_a = N_a - (N_a - m phi_a) / tau + dN_a                        (Eqs. collide, lbe)
+// with A+^i_a(q) = sum_j c^j_a Theta^i_j(q + c_a, q) (Eq. gamma) from per-row
+// tables (grids whose metric terms depend on q1 only).
+//
+// The equilibrium is the index sum of Eq. (equilibrium) contracted once per
+// cell into the symmetric tensors
+//   A2^ij = (g^ij - delta^ij) T0 + Ut^i Ut^j,
+//   B3^ijk = T0 [(g^ij Ut^k - delta^ij U^k) + (cyclic)] + Ut^i Ut^j Ut^k,
+//   V^i = sum_j B3^ijj,
+// so that per direction
+//   phi_a = w_a [1 + c.U / T0 + (c.A2.c / T0 - tr A2) / (2 T0)
+//               + (B3(c, c, c) - 3 T0 c.V) / (6 T0^3)],
+// the Hermite polynomials (c^i c^j / T0 - delta^ij) and
+// (c^i c^j c^k - T0 (c^i delta^jk + c^j delta^ki + c^k delta^ij)) contracted
+// with the symmetric tensors of the equilibrium.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "lbm3d_lattice.hpp"
+
+namespace lbm3 {
+
+enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_MOVING = 2 };
+
+// compile-time loop: f(std::integral_constant<int, I>) for I = B .. E - 1, so
+// every lattice constant indexed by I folds at compile time
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+// per-row table: g^11, g^12, g^13, g^22, g^23, g^33, then A+^i_a at 6 + 3 a + i
+constexpr int TW = 6 + 3 * Q;
+// per-cell geometry output: J, the six g^ij, A+ (3 Q)
+constexpr int GW = 1 + TW;
+
+struct Desc3 {
+    double *P[2];        // populations, element ((i n2 + j) Q + a) pitch + k
+    double *side[2];     // moving-wall side state [2 walls][3 fields: m, Ut^2, Ut^3][CMAX rows][n2][pitch]
+    const double *tab;   // per-row tables [n1][TW]
+    const double *Jrow;  // per-row volume [n1]
+    double *mom;         // moments output [7][ncell]: m, U^1..3, Ut^1..3
+    int n1, n2, n3, pitch;
+    long long ncell;
+    int periodic1, bc_lo, bc_hi;
+    double ut_lo[2], ut_hi[2];
+    double a[3], omega, kpi;
+};
+
+__host__ __device__ inline size_t pidx3(int n2, int pitch, int i, int j, int a, int k)
+{
+    return ((size_t)(i * n2 + j) * Q + a) * pitch + k;
+}
+__host__ __device__ inline size_t sidx3(int n2, int pitch, int wall, int field, int row, int j, int k)
+{
+    return (((size_t)(wall * 3 + field) * CMAX + row) * n2 + j) * pitch + k;
+}
+__device__ inline int wrap3(int x, int n)
+{
+    if (n >= CMAX) return x < 0 ? x + n : (x >= n ? x - n : x);
+    return ((x % n) + n) % n;
+}
+
+// Source of N_a(i, .): row r and direction beta of the post-collision field,
+// and the wall crossed (0 none, 1 low, 2 high); beyond a wall the mirror image
+// of the source row, with the reversed (no-slip) or specular (moving wall)
+// direction (App. B).
+__host__ __device__ inline void source_row(int i, int a, int n1, int per1, int bclo, int bchi, int &r, int &beta,
+                                           int &wall)
+{
+    const int ti = i - cvec(a, 0);
+    r = ti;
+    beta = a;
+    wall = 0;
+    if (ti < 0) {
+        if (per1) {
+            r = ti + n1;
+        } else {
+            r = -1 - ti;
+            wall = 1;
+            beta = bclo == BC_NOSLIP ? opp(a) : specular(a);
+        }
+    } else if (ti >= n1) {
+        if (per1) {
+            r = ti - n1;
+        } else {
+            r = 2 * n1 - 1 - ti;
+            wall = 2;
+            beta = bchi == BC_NOSLIP ? opp(a) : specular(a);
+        }
+    }
+}
+
+// the wave's cell: tile t = ((i n2 + j) nkb + kb), lanes along q3
+struct Cell3 {
+    int i, j, k;
+};
+__device__ inline bool cell_of(const Desc3 &d, Cell3 &c)
+{
+    const int nkb = (d.n3 + 63) >> 6;
+    const int t = (int)blockIdx.x;
+    const int kb = t % nkb, ij = t / nkb;
+    c.i = ij / d.n2;
+    c.j = ij - c.i * d.n2;
+    c.k = kb * 64 + (int)(threadIdx.x & 63);
+    return c.i < d.n1 && c.k < d.n3;
+}
+
+// the symmetric tensors of the equilibrium (unique components): A2 as
+// 11 12 13 22 23 33, tr A2, B3 as 111 112 113 122 123 133 222 223 233 333,
+// and V^i = sum_j B3^ijj
+struct EqT3 {
+    double A2[6], trA2, B3[10], V[3];
+};
+__host__ __device__ constexpr int sym2(int x, int y)
+{
+    return x <= y ? (x == 0 ? y : (x == 1 ? 2 + y : 5)) : sym2(y, x);
+}
+__host__ __device__ constexpr int sym3(int x, int y, int z)
+{
+    // sort (x, y, z), then index the 10 non-decreasing triples
+    return x > y ? sym3(y, x, z) : (y > z ? sym3(x, z, y) : (x == 0 ? (y == 0 ? z : (y == 1 ? 2 + z : 5)) : (x == 1 ? (y == 1 ? 5 + z : 8) : 9)));
+}
+__device__ __forceinline__ EqT3 eq_tensors(const double G[6], const double U[3], const double Ut[3])
+{
+    EqT3 E;
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = x; y < 3; ++y) E.A2[sym2(x, y)] = (G[sym2(x, y)] - (x == y ? 1.0 : 0.0)) * T0 + Ut[x] * Ut[y];
+    E.trA2 = E.A2[0] + E.A2[3] + E.A2[5];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = x; y < 3; ++y)
+#pragma unroll
+            for (int z = y; z < 3; ++z)
+                E.B3[sym3(x, y, z)] = T0 * ((G[sym2(x, y)] * Ut[z] - (x == y ? U[z] : 0.0)) +
+                                            (G[sym2(y, z)] * Ut[x] - (y == z ? U[x] : 0.0)) +
+                                            (G[sym2(z, x)] * Ut[y] - (z == x ? U[y] : 0.0))) +
+                                      Ut[x] * Ut[y] * Ut[z];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) E.V[x] = E.B3[sym3(x, 0, 0)] + E.B3[sym3(x, 1, 1)] + E.B3[sym3(x, 2, 2)];
+    return E;
+}
+// phi_a = J f^eq_a / m of Eq. (equilibrium) through the symmetric tensors
+template <int A>
+__device__ __forceinline__ double phi_dir(const EqT3 &E, const double U[3])
+{
+    constexpr int c0 = cvec(A, 0), c1 = cvec(A, 1), c2 = cvec(A, 2);
+    constexpr int cv[3] = {c0, c1, c2};
+    double cU = 0.0, cA2c = 0.0, B3c = 0.0, cV = 0.0;
+    sfor<0, 3>([&](auto X) {
+        constexpr int x = decltype(X)::value;
+        if constexpr (cv[x] != 0) {
+            cU += cv[x] * U[x];
+            cV += cv[x] * E.V[x];
+            sfor<0, 3>([&](auto Y) {
+                constexpr int y = decltype(Y)::value;
+                if constexpr (cv[y] != 0) {
+                    cA2c += (double)(cv[x] * cv[y]) * E.A2[sym2(x, y)];
+                    sfor<0, 3>([&](auto Z) {
+                        constexpr int z = decltype(Z)::value;
+                        if constexpr (cv[z] != 0) B3c += (double)(cv[x] * cv[y] * cv[z]) * E.B3[sym3(x, y, z)];
+                    });
+                }
+            });
+        }
+    });
+    return weight(A) * (1.0 + cU / T0 + (cA2c / T0 - E.trA2) / (2.0 * T0) + (B3c - 3.0 * T0 * cV) / (6.0 * T0 * T0 * T0));
+}
+
+// MOM = true writes the moments the next step would see instead of colliding
+template <bool MOM>
+__global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int par)
+{
+    const Desc3 &d = *dp;
+    Cell3 c;
+    if (!cell_of(d, c)) return;
+    const int pin = par & 1;
+    const double *__restrict__ P = d.P[pin];
+    const double *__restrict__ tb = d.tab + (size_t)c.i * TW;
+    const double *__restrict__ side_in = d.side[pin];
+
+    // ---- pull (Eq. adv, App. B) ----
+    double n[Q];
+    const bool nearwall = !d.periodic1 && (c.i < CMAX || c.i >= d.n1 - CMAX);
+    if (!nearwall) {
+        // every source row lies inside the grid (or wraps along a periodic q1)
+        sfor<0, Q>([&](auto Aic) {
+            constexpr int a = decltype(Aic)::value;
+            int r = c.i - cvec(a, 0);
+            if (d.periodic1) r = wrap3(r, d.n1);
+            const int jj = wrap3(c.j - cvec(a, 1), d.n2), kk = wrap3(c.k - cvec(a, 2), d.n3);
+            n[a] = P[pidx3(d.n2, d.pitch, r, jj, a, kk)];
+        });
+    } else {
+        sfor<0, Q>([&](auto Aic) {
+            constexpr int a = decltype(Aic)::value;
+            int r, beta, wall;
+            source_row(c.i, a, d.n1, d.periodic1, d.bc_lo, d.bc_hi, r, beta, wall);
+            const int jj = wrap3(c.j - cvec(a, 1), d.n2), kk = wrap3(c.k - cvec(a, 2), d.n3);
+            double v = P[pidx3(d.n2, d.pitch, r, jj, beta, kk)];
+            if constexpr (cvec(a, 1) != 0 || cvec(a, 2) != 0) {
+                if (wall != 0) {
+                    const int sd = wall - 1;
+                    if ((sd ? d.bc_hi : d.bc_lo) == BC_MOVING) {
+                        // App. B.3 correction, both tangential components
+                        const int row = sd ? d.n1 - 1 - r : r;
+                        const double mz = side_in[sidx3(d.n2, d.pitch, sd, 0, row, jj, kk)];
+                        const double U02 = sd ? d.ut_hi[0] : d.ut_lo[0], U03 = sd ? d.ut_hi[1] : d.ut_lo[1];
+                        double corr = 0.0;
+                        if constexpr (cvec(a, 1) != 0)
+                            corr += cvec(a, 1) * (U02 - side_in[sidx3(d.n2, d.pitch, sd, 1, row, jj, kk)]);
+                        if constexpr (cvec(a, 2) != 0)
+                            corr += cvec(a, 2) * (U03 - side_in[sidx3(d.n2, d.pitch, sd, 2, row, jj, kk)]);
+                        v += 2.0 * weight(a) / T0 * mz * corr;
+                    }
+                }
+            }
+            n[a] = v;
+        });
+    }
+
+    // ---- moments ----
+    double m = 0.0, mU[3] = {0.0, 0.0, 0.0};
+    sfor<0, Q>([&](auto Aic) {
+        constexpr int a = decltype(Aic)::value;
+        m += n[a];
+        if constexpr (cvec(a, 0) != 0) mU[0] += cvec(a, 0) * n[a];
+        if constexpr (cvec(a, 1) != 0) mU[1] += cvec(a, 1) * n[a];
+        if constexpr (cvec(a, 2) != 0) mU[2] += cvec(a, 2) * n[a];
+    });
+    const double im = 1.0 / m;
+    const double U[3] = {mU[0] * im, mU[1] * im, mU[2] * im};
+
+    // ---- force with the lagged own-cell populations N'(q, t-1) ----
+    double L[3] = {0.0, 0.0, 0.0};
+    sfor<1, Q>([&](auto Aic) {
+        constexpr int a = decltype(Aic)::value;
+        const double own = P[pidx3(d.n2, d.pitch, c.i, c.j, a, c.k)];
+        const double s = own + n[opp(a)];
+        L[0] += tb[6 + 3 * a + 0] * s;
+        L[1] += tb[6 + 3 * a + 1] * s;
+        L[2] += tb[6 + 3 * a + 2] * s;
+    });
+    double JF[3], Ut[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        JF[e] = -0.5 * L[e] + m * d.a[e];
+        Ut[e] = U[e] + 0.5 * JF[e] * im;
+    }
+    if constexpr (MOM) {
+        const size_t cell = ((size_t)c.i * d.n2 + c.j) * d.n3 + c.k, nc = (size_t)d.ncell;
+        d.mom[cell] = m;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            d.mom[(1 + e) * nc + cell] = U[e];
+            d.mom[(4 + e) * nc + cell] = Ut[e];
+        }
+        return;
+    } else {
+        // ---- equilibrium tensors of the cell (symmetric: unique components) ----
+        const double G[6] = {tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]};   // 11 12 13 22 23 33
+        const EqT3 E = eq_tensors(G, U, Ut);
+
+        // ---- the momentum-flux correction (m phi_a recomputed below) ----
+        double dPi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        sfor<1, Q>([&](auto Aic) {
+            constexpr int a = decltype(Aic)::value;
+            const double mp = m * phi_dir<a>(E, U);
+            double S[3];
+#pragma unroll
+            for (int y = 0; y < 3; ++y) S[y] = tb[6 + 3 * a + y] + tb[6 + 3 * opp(a) + y];
+            sfor<0, 3>([&](auto X) {
+                constexpr int x = decltype(X)::value;
+                if constexpr (cvec(a, x) != 0) {
+#pragma unroll
+                    for (int y = 0; y < 3; ++y) dPi[x][y] += cvec(a, x) * S[y] * mp;
+                }
+            });
+        });
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int y = 0; y < 3; ++y) dPi[x][y] *= d.kpi;
+        const double trPi = dPi[0][0] + dPi[1][1] + dPi[2][2];
+
+        // ---- correction, BGK, store ----
+        double *__restrict__ Pout = d.P[pin ^ 1];
+        sfor<0, Q>([&](auto Aic) {
+            constexpr int a = decltype(Aic)::value;
+            double t1 = 0.0, t2 = 0.0;
+            sfor<0, 3>([&](auto X) {
+                constexpr int x = decltype(X)::value;
+                if constexpr (cvec(a, x) != 0) {
+                    t1 += cvec(a, x) * JF[x];
+                    sfor<0, 3>([&](auto Y) {
+                        constexpr int y = decltype(Y)::value;
+                        if constexpr (cvec(a, y) != 0) t2 += (double)(cvec(a, x) * cvec(a, y)) * dPi[x][y];
+                    });
+                }
+            });
+            const double dN = weight(a) * (t1 / T0 + (t2 / T0 - trPi) / T0);
+            const double mp = m * phi_dir<a>(E, U);
+            Pout[pidx3(d.n2, d.pitch, c.i, c.j, a, c.k)] = n[a] - (n[a] - mp) * d.omega + dN;
+        });
+        // side state of the moving walls: m, Ut^2, Ut^3 of the rows a wall pulls from
+        double *__restrict__ so = d.side[pin ^ 1];
+        if (d.bc_lo == BC_MOVING && c.i < CMAX) {
+            so[sidx3(d.n2, d.pitch, 0, 0, c.i, c.j, c.k)] = m;
+            so[sidx3(d.n2, d.pitch, 0, 1, c.i, c.j, c.k)] = Ut[1];
+            so[sidx3(d.n2, d.pitch, 0, 2, c.i, c.j, c.k)] = Ut[2];
+        }
+        if (d.bc_hi == BC_MOVING && c.i >= d.n1 - CMAX) {
+            const int row = d.n1 - 1 - c.i;
+            so[sidx3(d.n2, d.pitch, 1, 0, row, c.j, c.k)] = m;
+            so[sidx3(d.n2, d.pitch, 1, 1, row, c.j, c.k)] = Ut[1];
+            so[sidx3(d.n2, d.pitch, 1, 2, row, c.j, c.k)] = Ut[2];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// set-up (FP64): tangents, metric, volume, co-tangents, Christoffel sums
+// ---------------------------------------------------------------------------
+// g_i = [x(q + e_i) - x(q - e_i)] / 2 on the halo range (Eqs. distance,
+// tangent); out[pos][9] = g_1, g_2, g_3; the outermost layer is left NaN
+__global__ void k_tangent3(const double *X, const double *Y, const double *Z, int H1, int H2, int H3, double *tg)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)H1 * H2 * H3;
+    if (p >= n) return;
+    const int c3 = (int)(p % H3), c2 = (int)((p / H3) % H2), c1 = (int)(p / ((long long)H2 * H3));
+    double *t = tg + p * 9;
+    if (c1 == 0 || c2 == 0 || c3 == 0 || c1 == H1 - 1 || c2 == H2 - 1 || c3 == H3 - 1) {
+        for (int e = 0; e < 9; ++e) t[e] = __builtin_nan("");
+        return;
+    }
+    const long long st[3] = {(long long)H2 * H3, H3, 1};
+    for (int i = 0; i < 3; ++i) {
+        const long long pp = p + st[i], pm = p - st[i];
+        t[3 * i + 0] = 0.5 * ((X[pp] - X[p]) - (X[pm] - X[p]));
+        t[3 * i + 1] = 0.5 * ((Y[pp] - Y[p]) - (Y[pm] - Y[p]));
+        t[3 * i + 2] = 0.5 * ((Z[pp] - Z[p]) - (Z[pm] - Z[p]));
+    }
+}
+
+__device__ inline void cross3(const double *u, const double *v, double *w)
+{
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+// per interior cell: out[cell][GW] = J, g^ij (6), A+^i_a (3 Q), with
+// J = (g_1 x g_2) . g_3 (Eq. metric), g^1 = (g_2 x g_3) / J and cyclic (Eq.
+// covectors), A+^i_a = g^i(q) . sum_j c^j_a [g_j(q + c_a) - g_j(q)] (Eq. gamma)
+__global__ void k_geom3(const double *tg, int n1, int n2, int n3, int h, double *out)
+{
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nc = (long long)n1 * n2 * n3;
+    if (cell >= nc) return;
+    const int k = (int)(cell % n3), j = (int)((cell / n3) % n2), i = (int)(cell / ((long long)n2 * n3));
+    const int H2 = n2 + 2 * h, H3 = n3 + 2 * h;
+    auto pos = [&](int a, int b, int cc) { return ((long long)a * H2 + b) * H3 + cc; };
+    const long long q = pos(i + h, j + h, k + h);
+    const double *g = tg + q * 9;
+    double x12[3], co[3][3];
+    cross3(g + 0, g + 3, x12);
+    const double J = x12[0] * g[6] + x12[1] * g[7] + x12[2] * g[8];
+    for (int m = 0; m < 3; ++m) {
+        cross3(g + 3 * ((m + 1) % 3), g + 3 * ((m + 2) % 3), co[m]);
+        for (int e = 0; e < 3; ++e) co[m][e] /= J;
+    }
+    double *o = out + cell * GW;
+    o[0] = J;
+    int f = 1;
+    for (int x = 0; x < 3; ++x)
+        for (int y = x; y < 3; ++y) o[f++] = co[x][0] * co[y][0] + co[x][1] * co[y][1] + co[x][2] * co[y][2];
+    for (int a = 0; a < Q; ++a) {
+        double dvec[3] = {0.0, 0.0, 0.0};
+        if (a > 0) {
+            const double *gp = tg + pos(i + h + cvec(a, 0), j + h + cvec(a, 1), k + h + cvec(a, 2)) * 9;
+            for (int jj = 0; jj < 3; ++jj) {
+                const int cj = cvec(a, jj);
+                if (cj == 0) continue;
+                for (int e = 0; e < 3; ++e) dvec[e] += cj * (gp[3 * jj + e] - g[3 * jj + e]);
+            }
+        }
+        for (int x = 0; x < 3; ++x) o[7 + 3 * a + x] = co[x][0] * dvec[0] + co[x][1] * dvec[1] + co[x][2] * dvec[2];
+    }
+}
+
+// flag[0] = 1 if some cell's g^ij or A+ differ from its row's first cell by
+// more than tol relative (the metric terms depend on more than q1); flag[1] =
+// 1 if J <= 0 or a value is not finite
+__global__ void k_rowcheck3(const double *geo, int n1, int n2, int n3, double tol, int *flag)
+{
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nc = (long long)n1 * n2 * n3;
+    if (cell >= nc) return;
+    const int i = (int)(cell / ((long long)n2 * n3));
+    const double *o = geo + cell * GW;
+    const double *r = geo + (long long)i * n2 * n3 * GW;
+    if (!(o[0] > 0.0)) atomicOr(flag + 1, 1);
+    double scale = 0.0;
+    for (int f = 1; f < GW; ++f) scale = fmax(scale, fabs(r[f]));
+    for (int f = 0; f < GW; ++f) {
+        if (!isfinite(o[f])) atomicOr(flag + 1, 1);
+        const double s = f == 0 ? fabs(r[0]) : scale;
+        if (fabs(o[f] - r[f]) > tol * s) atomicOr(flag, 1);
+    }
+}
+
+// per-row tables and volume from the first cell of each row
+__global__ void k_rowtab3(const double *geo, int n1, int n2, int n3, double *tab, double *Jrow)
+{
+    const int i = (int)blockIdx.x;
+    if (i >= n1) return;
+    const double *r = geo + (long long)i * n2 * n3 * GW;
+    for (int f = (int)threadIdx.x; f < TW; f += (int)blockDim.x) tab[(size_t)i * TW + f] = r[1 + f];
+    if (threadIdx.x == 0) Jrow[i] = r[0];
+}
+
+// initial state N = J f^eq(rho0, U = Ut = u0; g^ij) (u0 may be null: rest);
+// side state m = J rho0, Ut = u0
+__global__ __launch_bounds__(64) void k_init3(const Desc3 *__restrict__ dp, const double *u0, double rho0)
+{
+    const Desc3 &d = *dp;
+    Cell3 c;
+    if (!cell_of(d, c)) return;
+    const size_t cell = ((size_t)c.i * d.n2 + c.j) * d.n3 + c.k;
+    const double *tb = d.tab + (size_t)c.i * TW;
+    double U[3] = {0.0, 0.0, 0.0};
+    if (u0)
+        for (int e = 0; e < 3; ++e) U[e] = u0[cell * 3 + e];
+    const double G[6] = {tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]};
+    const EqT3 E = eq_tensors(G, U, U);
+    const double m = d.Jrow[c.i] * rho0;
+    sfor<0, Q>([&](auto Aic) {
+        constexpr int a = decltype(Aic)::value;
+        d.P[0][pidx3(d.n2, d.pitch, c.i, c.j, a, c.k)] = m * phi_dir<a>(E, U);
+    });
+    if (c.i < CMAX) {
+        d.side[0][sidx3(d.n2, d.pitch, 0, 0, c.i, c.j, c.k)] = m;
+        d.side[0][sidx3(d.n2, d.pitch, 0, 1, c.i, c.j, c.k)] = U[1];
+        d.side[0][sidx3(d.n2, d.pitch, 0, 2, c.i, c.j, c.k)] = U[2];
+    }
+    if (c.i >= d.n1 - CMAX) {
+        const int row = d.n1 - 1 - c.i;
+        d.side[0][sidx3(d.n2, d.pitch, 1, 0, row, c.j, c.k)] = m;
+        d.side[0][sidx3(d.n2, d.pitch, 1, 1, row, c.j, c.k)] = U[1];
+        d.side[0][sidx3(d.n2, d.pitch, 1, 2, row, c.j, c.k)] = U[2];
+    }
+}
+
+// state <-> host layout [Q][ncell] (to_device = 0: out; 1: in)
+__global__ __launch_bounds__(64) void k_state3(const Desc3 *__restrict__ dp, int pin, double *host, int to_device)
+{
+    const Desc3 &d = *dp;
+    Cell3 c;
+    if (!cell_of(d, c)) return;
+    const size_t cell = ((size_t)c.i * d.n2 + c.j) * d.n3 + c.k;
+    for (int a = 0; a < Q; ++a) {
+        double &v = d.P[pin][pidx3(d.n2, d.pitch, c.i, c.j, a, c.k)];
+        if (to_device) v = host[(size_t)a * d.ncell + cell];
+        else host[(size_t)a * d.ncell + cell] = v;
+    }
+}
+
+// side state <-> host layout [2 walls][3 fields][CMAX rows][n2][n3]
+__global__ void k_side3(const Desc3 *__restrict__ dp, int pin, double *host, int to_device)
+{
+    const Desc3 &d = *dp;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = 2LL * 3 * CMAX * d.n2 * d.n3;
+    if (t >= n) return;
+    const int k = (int)(t % d.n3);
+    const long long rest = t / d.n3;
+    const int j = (int)(rest % d.n2);
+    const long long wfr = rest / d.n2;   // ((wall * 3 + field) * CMAX + row)
+    double &v = d.side[pin][(size_t)(wfr * d.n2 + j) * d.pitch + k];
+    if (to_device) v = host[t];
+    else host[t] = v;
+}
+
+// the streaming map the step uses: source cell, source direction, wall
+__global__ __launch_bounds__(64) void k_stream_map3(const Desc3 *__restrict__ dp, int *sc, int *sd, int *wl)
+{
+    const Desc3 &d = *dp;
+    Cell3 c;
+    if (!cell_of(d, c)) return;
+    const size_t cell = ((size_t)c.i * d.n2 + c.j) * d.n3 + c.k;
+    for (int a = 0; a < Q; ++a) {
+        int r, beta, wall;
+        source_row(c.i, a, d.n1, d.periodic1, d.bc_lo, d.bc_hi, r, beta, wall);
+        const int jj = wrap3(c.j - cvec(a, 1), d.n2), kk = wrap3(c.k - cvec(a, 2), d.n3);
+        sc[cell * Q + a] = (int)(((size_t)r * d.n2 + jj) * d.n3 + kk);
+        sd[cell * Q + a] = beta;
+        wl[cell * Q + a] = wall;
+    }
+}
+
+} // namespace lbm3

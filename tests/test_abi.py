@@ -20,12 +20,24 @@ def lib():
 
 
 def test_exports_every_declared_symbol(lib):
-    hdr = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    names = set(re.findall(r"^\s*(?:int|void|const char|void \*)\s*\*?\s*(lbm_\w+)\s*\(", hdr, re.M))
-    assert len(names) >= 20
+    from paper_2301_01868_amd import lbm3d
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            hdr = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"^\s*(?:int|void|const char|void \*)\s*\*?\s*(lbm\w*_\w+)\s*\(", hdr, re.M))
+    assert len(names) >= 30 and "lbm3d_step" in names
     for n in names:
         assert hasattr(lib, n), n
-    assert names <= set(lbm.EXPORTED) | {"lbm_lattice"}
+    assert names <= set(lbm.EXPORTED) | set(lbm3d.EXPORTED) | {"lbm_lattice"}
+
+
+def test_library_3d_lattice_agrees_with_oracle(lib):
+    from paper_2301_01868_amd import lbm3d
+    from oracle.oracle3d import lattice3
+    c, w, T0 = lbm3d.lbm3d_lattice()
+    oc, ow, oT0 = lattice3()
+    assert np.array_equal(c, oc) and np.array_equal(w, ow) and T0 == oT0
 
 
 def test_library_lattice_tables_agree_with_oracle(lib):
