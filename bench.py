@@ -1,7 +1,7 @@
 """Throughput benchmark of the curvilinear lattice Boltzmann step on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                [--geometry auto|cell|cell_table] [--iterations K] [--no-fp64] [--no-fp16] [--no-cpu]
+                [--geometry auto|cell|cell_table] [--iterations K] [--no-fp64] [--no-fp16] [--no-3d] [--no-cpu]
 python bench.py --serve [--rate R] [--duration S] [--no-sequential]
 
 FP32 populations give the headline figure; the same workload is then timed
@@ -225,6 +225,42 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
             "roofline": roof, "unbatched": seq}
 
 
+def measure3d(steps, warmup, stream):
+    """The 3D step (39-velocity lattice, FP64) on a cylinder section continued
+    along z: 128 radial x 512 azimuthal x 64 axial cells (4.19 M), radii 128 to
+    256 lattice units, inner wall rotating at 0.05, tau 0.8; timed with HIP
+    events on the grid's stream after warm-up steps."""
+    import torch
+    from paper_2301_01868_amd import grids3d as G3
+    from paper_2301_01868_amd import lbm3d
+
+    case = G3.circular_couette3(128, 512, 128.0, n3=64, dz=1.0, u_inner=0.05, tau=0.8)
+    g = lbm3d.Grid3(case, stream=ct_stream(stream))
+    g.init()
+    g.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    g.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    m, U, Ut = g.moments()
+    bad = int((~np.isfinite(m)).sum() + (m <= 0).sum())
+    g.close()
+    cells = case.ncell
+    alg = 2 * 39 * 8 * cells          # one read and one write of every FP64 population
+    achieved = alg / (ms / steps * 1e-3) / 1e9
+    return {"value": round(cells * steps / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(ms / steps, 5), "cells": cells, "bad_cells_after": bad,
+            "workload": "cylinder_couette_128x512x64 (D3Q39, FP64)",
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "k_step3 (D3Q39, f64)", "bytes_per_launch": alg,
+                         "avg_launch_us": round(ms / steps * 1e3, 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +271,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D (D3Q39, FP64) leg")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: continuous batching vs sequential FP64 on a Poisson trace")
     ap.add_argument("--rate", type=float, default=50.0)
@@ -318,6 +355,10 @@ def main():
         r16 = measure(cases, lbm.LBM_FP16, args.steps, args.warmup, args.wpb, stream, args.workload, iterations=it,
                       geometry=geom)
 
+    r3 = None
+    if not args.no_3d and it == 0 and geom == lbm.LBM_GEOM_AUTO:
+        r3 = measure3d(max(4, args.steps // 2), max(2, args.warmup // 2), stream)
+
     cpu = None
     if not args.no_cpu:
         q21 = sorted([c for c in cases if c.q == 21] or cases, key=lambda c: c.ncell)
@@ -351,6 +392,8 @@ def main():
     if r16 is not None:
         out["fp16"] = {"value": round(r16["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r16["ms_per_step"], 5),
                        "roofline": r16["roofline"], "bad_cells_after": r16["bad_cells"]}
+    if r3 is not None:
+        out["d3q39_fp64"] = r3
     print(json.dumps(out), flush=True)
 
 

@@ -12,7 +12,9 @@
 //   dN_a = w_a [c.JF / T0 + (c^j c^k / T0 - delta^jk) J dPi^jk / T0]          (Eq. deltaN)
 //   N'_a = N_a - (N_a - m phi_a) / tau + dN_a                        (Eqs. collide, lbe)
 // with A+^i_a(q) = sum_j c^j_a Theta^i_j(q + c_a, q) (Eq. gamma) from per-row
-// tables (grids whose metric terms depend on q1 only).
+// tables (grids whose metric terms depend on q1 only).  The lagged sum
+// sum_a A+^i_a N'_a(q, t-1) is formed by the step that produces N'(q, t-1)
+// and kept as three values per cell.
 //
 // The equilibrium is the index sum of Eq. (equilibrium) contracted once per
 // cell into the symmetric tensors
@@ -49,14 +51,29 @@ __device__ __forceinline__ void sfor(F &&f)
     }
 }
 
-// per-row table: g^11, g^12, g^13, g^22, g^23, g^33, then A+^i_a at 6 + 3 a + i
-constexpr int TW = 6 + 3 * Q;
+// The equilibrium as a polynomial in c: phi_a = w_a sum_k K_k P_k(c_a) over
+// the 20 monomials P_k of degree <= 3 (1; c_x; c_x c_y for x <= y; c_x c_y c_z
+// for x <= y <= z), with per-cell coefficients K from U, Ut and g^ij.  The
+// momentum-flux correction is then a per-row moment table contracted with K:
+//   J dPi^ij = kpi m sum_k K_k T^ij_k,  T^ij_k = sum_a w_a c^i_a S^j_a P_k(c_a),
+// S^j_a = A+^j_a + A+^j_{-a}, the same sum over directions in another order.
+constexpr int NK = 20;
+// per-row table: g^11, g^12, g^13, g^22, g^23, g^33; A+^i_a at 6 + 3 a + i;
+// T^ij_k at TT + (3 i + j) NK + k
+constexpr int TG = 6 + 3 * Q;
+constexpr int TT = TG;
+constexpr int TW = TG + 9 * NK;
 // per-cell geometry output: J, the six g^ij, A+ (3 Q)
-constexpr int GW = 1 + TW;
+constexpr int GW = 1 + TG;
+
+// uniform (scalar-cache) view of constant data: the descriptor and the per-row tables
+template <typename T>
+using cptr3 = const __attribute__((address_space(4))) T *;
 
 struct Desc3 {
     double *P[2];        // populations, element ((i n2 + j) Q + a) pitch + k
     double *side[2];     // moving-wall side state [2 walls][3 fields: m, Ut^2, Ut^3][CMAX rows][n2][pitch]
+    double *lag[2];      // lagged own-cell force sums sum_a A+^i_a N'_a, [3][n1 n2][pitch]
     const double *tab;   // per-row tables [n1][TW]
     const double *Jrow;  // per-row volume [n1]
     double *mom;         // moments output [7][ncell]: m, U^1..3, Ut^1..3
@@ -115,23 +132,18 @@ __host__ __device__ inline void source_row(int i, int a, int n1, int per1, int b
 struct Cell3 {
     int i, j, k;
 };
-__device__ inline bool cell_of(const Desc3 &d, Cell3 &c)
+__device__ inline bool cell_of(int n1, int n2, int n3, Cell3 &c)
 {
-    const int nkb = (d.n3 + 63) >> 6;
+    const int nkb = (n3 + 63) >> 6;
     const int t = (int)blockIdx.x;
     const int kb = t % nkb, ij = t / nkb;
-    c.i = ij / d.n2;
-    c.j = ij - c.i * d.n2;
+    c.i = ij / n2;
+    c.j = ij - c.i * n2;
     c.k = kb * 64 + (int)(threadIdx.x & 63);
-    return c.i < d.n1 && c.k < d.n3;
+    return c.i < n1 && c.k < n3;
 }
+__device__ inline bool cell_of(const Desc3 &d, Cell3 &c) { return cell_of(d.n1, d.n2, d.n3, c); }
 
-// the symmetric tensors of the equilibrium (unique components): A2 as
-// 11 12 13 22 23 33, tr A2, B3 as 111 112 113 122 123 133 222 223 233 333,
-// and V^i = sum_j B3^ijj
-struct EqT3 {
-    double A2[6], trA2, B3[10], V[3];
-};
 __host__ __device__ constexpr int sym2(int x, int y)
 {
     return x <= y ? (x == 0 ? y : (x == 1 ? 2 + y : 5)) : sym2(y, x);
@@ -141,99 +153,123 @@ __host__ __device__ constexpr int sym3(int x, int y, int z)
     // sort (x, y, z), then index the 10 non-decreasing triples
     return x > y ? sym3(y, x, z) : (y > z ? sym3(x, z, y) : (x == 0 ? (y == 0 ? z : (y == 1 ? 2 + z : 5)) : (x == 1 ? (y == 1 ? 5 + z : 8) : 9)));
 }
-__device__ __forceinline__ EqT3 eq_tensors(const double G[6], const double U[3], const double Ut[3])
+// monomial k of c (k = 0: 1; 1..3: c_x; 4..9: c_x c_y, x <= y; 10..19:
+// c_x c_y c_z, x <= y <= z, in the sym2 / sym3 orders) and its multiplicity
+// in a symmetric contraction
+__host__ __device__ constexpr int mono(int k, int c0, int c1, int c2)
 {
-    EqT3 E;
-#pragma unroll
-    for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int y = x; y < 3; ++y) E.A2[sym2(x, y)] = (G[sym2(x, y)] - (x == y ? 1.0 : 0.0)) * T0 + Ut[x] * Ut[y];
-    E.trA2 = E.A2[0] + E.A2[3] + E.A2[5];
-#pragma unroll
-    for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int y = x; y < 3; ++y)
-#pragma unroll
-            for (int z = y; z < 3; ++z)
-                E.B3[sym3(x, y, z)] = T0 * ((G[sym2(x, y)] * Ut[z] - (x == y ? U[z] : 0.0)) +
-                                            (G[sym2(y, z)] * Ut[x] - (y == z ? U[x] : 0.0)) +
-                                            (G[sym2(z, x)] * Ut[y] - (z == x ? U[y] : 0.0))) +
-                                      Ut[x] * Ut[y] * Ut[z];
-#pragma unroll
-    for (int x = 0; x < 3; ++x) E.V[x] = E.B3[sym3(x, 0, 0)] + E.B3[sym3(x, 1, 1)] + E.B3[sym3(x, 2, 2)];
-    return E;
+    const int c[3] = {c0, c1, c2};
+    if (k == 0) return 1;
+    if (k < 4) return c[k - 1];
+    if (k < 10) {
+        constexpr int px[6] = {0, 0, 0, 1, 1, 2}, py[6] = {0, 1, 2, 1, 2, 2};
+        return c[px[k - 4]] * c[py[k - 4]];
+    }
+    constexpr int tx[10] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 2}, ty[10] = {0, 0, 0, 1, 1, 2, 1, 1, 2, 2},
+                  tz[10] = {0, 1, 2, 1, 2, 2, 1, 2, 2, 2};
+    return c[tx[k - 10]] * c[ty[k - 10]] * c[tz[k - 10]];
 }
-// phi_a = J f^eq_a / m of Eq. (equilibrium) through the symmetric tensors
-template <int A>
-__device__ __forceinline__ double phi_dir(const EqT3 &E, const double U[3])
+__host__ __device__ constexpr int mult(int k)
 {
-    constexpr int c0 = cvec(A, 0), c1 = cvec(A, 1), c2 = cvec(A, 2);
-    constexpr int cv[3] = {c0, c1, c2};
-    double cU = 0.0, cA2c = 0.0, B3c = 0.0, cV = 0.0;
+    constexpr int m2[6] = {1, 2, 2, 1, 2, 1};
+    constexpr int m3[10] = {1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
+    return k < 4 ? 1 : (k < 10 ? m2[k - 4] : m3[k - 10]);
+}
+
+// Coefficients K of phi_a = w_a sum_k K_k P_k(c_a) (see NK): the index sum of
+// Eq. (equilibrium) contracted into the symmetric tensors
+//   A2^xy = (g^xy - delta^xy) T0 + Ut^x Ut^y,
+//   B3^xyz = T0 [(g^xy Ut^z - delta^xy U^z) + (cyclic)] + Ut^x Ut^y Ut^z,
+//   V^x = sum_y B3^xyy,
+// through the Hermite polynomials: K_0 = 1 - tr A2 / (2 T0),
+// K_x = U^x / T0 - V^x / (2 T0^2), K_xy = mult A2^xy / (2 T0^2),
+// K_xyz = mult B3^xyz / (6 T0^3).  G holds g^11 g^12 g^13 g^22 g^23 g^33.
+__device__ __forceinline__ void eq_coeffs(const double G[6], const double U[3], const double Ut[3], double K[NK])
+{
+    double trA2 = 0.0, V[3] = {0.0, 0.0, 0.0};
     sfor<0, 3>([&](auto X) {
         constexpr int x = decltype(X)::value;
-        if constexpr (cv[x] != 0) {
-            cU += cv[x] * U[x];
-            cV += cv[x] * E.V[x];
-            sfor<0, 3>([&](auto Y) {
-                constexpr int y = decltype(Y)::value;
-                if constexpr (cv[y] != 0) {
-                    cA2c += (double)(cv[x] * cv[y]) * E.A2[sym2(x, y)];
-                    sfor<0, 3>([&](auto Z) {
-                        constexpr int z = decltype(Z)::value;
-                        if constexpr (cv[z] != 0) B3c += (double)(cv[x] * cv[y] * cv[z]) * E.B3[sym3(x, y, z)];
-                    });
-                }
+        sfor<x, 3>([&](auto Y) {
+            constexpr int y = decltype(Y)::value;
+            const double a2 = (G[sym2(x, y)] - (x == y ? 1.0 : 0.0)) * T0 + Ut[x] * Ut[y];
+            if constexpr (x == y) trA2 += a2;
+            K[4 + sym2(x, y)] = mult(4 + sym2(x, y)) * a2 / (2.0 * T0 * T0);
+            sfor<y, 3>([&](auto Z) {
+                constexpr int z = decltype(Z)::value;
+                const double b3 = T0 * ((G[sym2(x, y)] * Ut[z] - (x == y ? U[z] : 0.0)) +
+                                        (G[sym2(y, z)] * Ut[x] - (y == z ? U[x] : 0.0)) +
+                                        (G[sym2(z, x)] * Ut[y] - (z == x ? U[y] : 0.0))) +
+                                  Ut[x] * Ut[y] * Ut[z];
+                K[10 + sym3(x, y, z)] = mult(10 + sym3(x, y, z)) * b3 / (6.0 * T0 * T0 * T0);
+                // V^w = sum_v B3^wvv: this (x, y, z) contributes where two indices agree
+                if constexpr (x == y && y == z) V[x] += b3;
+                else if constexpr (x == y) V[z] += b3;
+                else if constexpr (y == z) V[x] += b3;
             });
-        }
+        });
     });
-    return weight(A) * (1.0 + cU / T0 + (cA2c / T0 - E.trA2) / (2.0 * T0) + (B3c - 3.0 * T0 * cV) / (6.0 * T0 * T0 * T0));
+    K[0] = 1.0 - trA2 / (2.0 * T0);
+    sfor<0, 3>([&](auto X) {
+        constexpr int x = decltype(X)::value;
+        K[1 + x] = U[x] / T0 - V[x] / (2.0 * T0 * T0);
+    });
+}
+template <int A>
+__device__ __forceinline__ double phi_poly(const double K[NK])
+{
+    double s = 0.0;
+    sfor<0, NK>([&](auto Kc) {
+        constexpr int k = decltype(Kc)::value;
+        constexpr int p = mono(k, cvec(A, 0), cvec(A, 1), cvec(A, 2));
+        if constexpr (p != 0) s += (double)p * K[k];
+    });
+    return weight(A) * s;
 }
 
 // MOM = true writes the moments the next step would see instead of colliding
 template <bool MOM>
 __global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int par)
 {
-    const Desc3 &d = *dp;
+    const cptr3<Desc3> d = (cptr3<Desc3>)dp;
     Cell3 c;
-    if (!cell_of(d, c)) return;
+    if (!cell_of(d->n1, d->n2, d->n3, c)) return;
     const int pin = par & 1;
-    const double *__restrict__ P = d.P[pin];
-    const double *__restrict__ tb = d.tab + (size_t)c.i * TW;
-    const double *__restrict__ side_in = d.side[pin];
+    const double *__restrict__ P = d->P[pin];
+    const cptr3<double> tb = (cptr3<double>)(d->tab + (size_t)c.i * TW);
+    const double *__restrict__ side_in = d->side[pin];
 
     // ---- pull (Eq. adv, App. B) ----
     double n[Q];
-    const bool nearwall = !d.periodic1 && (c.i < CMAX || c.i >= d.n1 - CMAX);
+    const bool nearwall = !d->periodic1 && (c.i < CMAX || c.i >= d->n1 - CMAX);
     if (!nearwall) {
         // every source row lies inside the grid (or wraps along a periodic q1)
         sfor<0, Q>([&](auto Aic) {
             constexpr int a = decltype(Aic)::value;
             int r = c.i - cvec(a, 0);
-            if (d.periodic1) r = wrap3(r, d.n1);
-            const int jj = wrap3(c.j - cvec(a, 1), d.n2), kk = wrap3(c.k - cvec(a, 2), d.n3);
-            n[a] = P[pidx3(d.n2, d.pitch, r, jj, a, kk)];
+            if (d->periodic1) r = wrap3(r, d->n1);
+            const int jj = wrap3(c.j - cvec(a, 1), d->n2), kk = wrap3(c.k - cvec(a, 2), d->n3);
+            n[a] = P[pidx3(d->n2, d->pitch, r, jj, a, kk)];
         });
     } else {
         sfor<0, Q>([&](auto Aic) {
             constexpr int a = decltype(Aic)::value;
             int r, beta, wall;
-            source_row(c.i, a, d.n1, d.periodic1, d.bc_lo, d.bc_hi, r, beta, wall);
-            const int jj = wrap3(c.j - cvec(a, 1), d.n2), kk = wrap3(c.k - cvec(a, 2), d.n3);
-            double v = P[pidx3(d.n2, d.pitch, r, jj, beta, kk)];
+            source_row(c.i, a, d->n1, d->periodic1, d->bc_lo, d->bc_hi, r, beta, wall);
+            const int jj = wrap3(c.j - cvec(a, 1), d->n2), kk = wrap3(c.k - cvec(a, 2), d->n3);
+            double v = P[pidx3(d->n2, d->pitch, r, jj, beta, kk)];
             if constexpr (cvec(a, 1) != 0 || cvec(a, 2) != 0) {
                 if (wall != 0) {
                     const int sd = wall - 1;
-                    if ((sd ? d.bc_hi : d.bc_lo) == BC_MOVING) {
+                    if ((sd ? d->bc_hi : d->bc_lo) == BC_MOVING) {
                         // App. B.3 correction, both tangential components
-                        const int row = sd ? d.n1 - 1 - r : r;
-                        const double mz = side_in[sidx3(d.n2, d.pitch, sd, 0, row, jj, kk)];
-                        const double U02 = sd ? d.ut_hi[0] : d.ut_lo[0], U03 = sd ? d.ut_hi[1] : d.ut_lo[1];
+                        const int row = sd ? d->n1 - 1 - r : r;
+                        const double mz = side_in[sidx3(d->n2, d->pitch, sd, 0, row, jj, kk)];
+                        const double U02 = sd ? d->ut_hi[0] : d->ut_lo[0], U03 = sd ? d->ut_hi[1] : d->ut_lo[1];
                         double corr = 0.0;
                         if constexpr (cvec(a, 1) != 0)
-                            corr += cvec(a, 1) * (U02 - side_in[sidx3(d.n2, d.pitch, sd, 1, row, jj, kk)]);
+                            corr += cvec(a, 1) * (U02 - side_in[sidx3(d->n2, d->pitch, sd, 1, row, jj, kk)]);
                         if constexpr (cvec(a, 2) != 0)
-                            corr += cvec(a, 2) * (U03 - side_in[sidx3(d.n2, d.pitch, sd, 2, row, jj, kk)]);
+                            corr += cvec(a, 2) * (U03 - side_in[sidx3(d->n2, d->pitch, sd, 2, row, jj, kk)]);
                         v += 2.0 * weight(a) / T0 * mz * corr;
                     }
                 }
@@ -254,60 +290,54 @@ __global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int 
     const double im = 1.0 / m;
     const double U[3] = {mU[0] * im, mU[1] * im, mU[2] * im};
 
-    // ---- force with the lagged own-cell populations N'(q, t-1) ----
-    double L[3] = {0.0, 0.0, 0.0};
+    // ---- force: the lagged own-cell sums sum_a A+_a N'_a(q, t-1), formed when
+    // the previous step produced N'(q, t-1), plus sum_a A+_a N_{-a}(q, t) ----
+    const size_t lrow = ((size_t)c.i * d->n2 + c.j) * d->pitch + c.k, lpl = (size_t)d->n1 * d->n2 * d->pitch;
+    double L[3] = {d->lag[pin][lrow], d->lag[pin][lpl + lrow], d->lag[pin][2 * lpl + lrow]};
     sfor<1, Q>([&](auto Aic) {
         constexpr int a = decltype(Aic)::value;
-        const double own = P[pidx3(d.n2, d.pitch, c.i, c.j, a, c.k)];
-        const double s = own + n[opp(a)];
-        L[0] += tb[6 + 3 * a + 0] * s;
-        L[1] += tb[6 + 3 * a + 1] * s;
-        L[2] += tb[6 + 3 * a + 2] * s;
+        L[0] += tb[6 + 3 * a + 0] * n[opp(a)];
+        L[1] += tb[6 + 3 * a + 1] * n[opp(a)];
+        L[2] += tb[6 + 3 * a + 2] * n[opp(a)];
+        __builtin_amdgcn_sched_barrier(0);
     });
     double JF[3], Ut[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-        JF[e] = -0.5 * L[e] + m * d.a[e];
+        JF[e] = -0.5 * L[e] + m * d->a[e];
         Ut[e] = U[e] + 0.5 * JF[e] * im;
     }
     if constexpr (MOM) {
-        const size_t cell = ((size_t)c.i * d.n2 + c.j) * d.n3 + c.k, nc = (size_t)d.ncell;
-        d.mom[cell] = m;
+        const size_t cell = ((size_t)c.i * d->n2 + c.j) * d->n3 + c.k, nc = (size_t)d->ncell;
+        d->mom[cell] = m;
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
-            d.mom[(1 + e) * nc + cell] = U[e];
-            d.mom[(4 + e) * nc + cell] = Ut[e];
+            d->mom[(1 + e) * nc + cell] = U[e];
+            d->mom[(4 + e) * nc + cell] = Ut[e];
         }
         return;
     } else {
-        // ---- equilibrium tensors of the cell (symmetric: unique components) ----
+        // ---- equilibrium coefficients of the cell ----
         const double G[6] = {tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]};   // 11 12 13 22 23 33
-        const EqT3 E = eq_tensors(G, U, Ut);
-
-        // ---- the momentum-flux correction (m phi_a recomputed below) ----
-        double dPi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        sfor<1, Q>([&](auto Aic) {
-            constexpr int a = decltype(Aic)::value;
-            const double mp = m * phi_dir<a>(E, U);
-            double S[3];
-#pragma unroll
-            for (int y = 0; y < 3; ++y) S[y] = tb[6 + 3 * a + y] + tb[6 + 3 * opp(a) + y];
-            sfor<0, 3>([&](auto X) {
-                constexpr int x = decltype(X)::value;
-                if constexpr (cvec(a, x) != 0) {
-#pragma unroll
-                    for (int y = 0; y < 3; ++y) dPi[x][y] += cvec(a, x) * S[y] * mp;
-                }
-            });
-        });
+        double K[NK];
+        eq_coeffs(G, U, Ut, K);
+        // ---- the momentum-flux correction through the per-row moment table ----
+        double dPi[3][3];
 #pragma unroll
         for (int x = 0; x < 3; ++x)
 #pragma unroll
-            for (int y = 0; y < 3; ++y) dPi[x][y] *= d.kpi;
+            for (int y = 0; y < 3; ++y) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < NK; ++k) s += tb[TT + (3 * x + y) * NK + k] * K[k];
+                dPi[x][y] = d->kpi * m * s;
+                __builtin_amdgcn_sched_barrier(0);
+            }
         const double trPi = dPi[0][0] + dPi[1][1] + dPi[2][2];
 
-        // ---- correction, BGK, store ----
-        double *__restrict__ Pout = d.P[pin ^ 1];
+        // ---- correction, BGK, store; the next step's lagged force sums ----
+        double *__restrict__ Pout = d->P[pin ^ 1];
+        double Ln[3] = {0.0, 0.0, 0.0};
         sfor<0, Q>([&](auto Aic) {
             constexpr int a = decltype(Aic)::value;
             double t1 = 0.0, t2 = 0.0;
@@ -322,21 +352,33 @@ __global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int 
                 }
             });
             const double dN = weight(a) * (t1 / T0 + (t2 / T0 - trPi) / T0);
-            const double mp = m * phi_dir<a>(E, U);
-            Pout[pidx3(d.n2, d.pitch, c.i, c.j, a, c.k)] = n[a] - (n[a] - mp) * d.omega + dN;
+            const double mp = m * phi_poly<a>(K);
+            const double np = n[a] - (n[a] - mp) * d->omega + dN;
+            Pout[pidx3(d->n2, d->pitch, c.i, c.j, a, c.k)] = np;
+            if constexpr (a > 0) {
+                Ln[0] += tb[6 + 3 * a + 0] * np;
+                Ln[1] += tb[6 + 3 * a + 1] * np;
+                Ln[2] += tb[6 + 3 * a + 2] * np;
+            }
+            // one direction at a time: without this boundary the scheduler
+            // starts every direction's arithmetic at once and runs out of registers
+            __builtin_amdgcn_sched_barrier(0);
         });
+        d->lag[pin ^ 1][lrow] = Ln[0];
+        d->lag[pin ^ 1][lpl + lrow] = Ln[1];
+        d->lag[pin ^ 1][2 * lpl + lrow] = Ln[2];
         // side state of the moving walls: m, Ut^2, Ut^3 of the rows a wall pulls from
-        double *__restrict__ so = d.side[pin ^ 1];
-        if (d.bc_lo == BC_MOVING && c.i < CMAX) {
-            so[sidx3(d.n2, d.pitch, 0, 0, c.i, c.j, c.k)] = m;
-            so[sidx3(d.n2, d.pitch, 0, 1, c.i, c.j, c.k)] = Ut[1];
-            so[sidx3(d.n2, d.pitch, 0, 2, c.i, c.j, c.k)] = Ut[2];
+        double *__restrict__ so = d->side[pin ^ 1];
+        if (d->bc_lo == BC_MOVING && c.i < CMAX) {
+            so[sidx3(d->n2, d->pitch, 0, 0, c.i, c.j, c.k)] = m;
+            so[sidx3(d->n2, d->pitch, 0, 1, c.i, c.j, c.k)] = Ut[1];
+            so[sidx3(d->n2, d->pitch, 0, 2, c.i, c.j, c.k)] = Ut[2];
         }
-        if (d.bc_hi == BC_MOVING && c.i >= d.n1 - CMAX) {
-            const int row = d.n1 - 1 - c.i;
-            so[sidx3(d.n2, d.pitch, 1, 0, row, c.j, c.k)] = m;
-            so[sidx3(d.n2, d.pitch, 1, 1, row, c.j, c.k)] = Ut[1];
-            so[sidx3(d.n2, d.pitch, 1, 2, row, c.j, c.k)] = Ut[2];
+        if (d->bc_hi == BC_MOVING && c.i >= d->n1 - CMAX) {
+            const int row = d->n1 - 1 - c.i;
+            so[sidx3(d->n2, d->pitch, 1, 0, row, c.j, c.k)] = m;
+            so[sidx3(d->n2, d->pitch, 1, 1, row, c.j, c.k)] = Ut[1];
+            so[sidx3(d->n2, d->pitch, 1, 2, row, c.j, c.k)] = Ut[2];
         }
     }
 }
@@ -433,14 +475,45 @@ __global__ void k_rowcheck3(const double *geo, int n1, int n2, int n3, double to
     }
 }
 
-// per-row tables and volume from the first cell of each row
+// per-row tables and volume from the first cell of each row, and the moment
+// table T^ij_k = sum_a w_a c^i_a (A+^j_a + A+^j_{-a}) P_k(c_a)
 __global__ void k_rowtab3(const double *geo, int n1, int n2, int n3, double *tab, double *Jrow)
 {
     const int i = (int)blockIdx.x;
     if (i >= n1) return;
     const double *r = geo + (long long)i * n2 * n3 * GW;
-    for (int f = (int)threadIdx.x; f < TW; f += (int)blockDim.x) tab[(size_t)i * TW + f] = r[1 + f];
+    for (int f = (int)threadIdx.x; f < TG; f += (int)blockDim.x) tab[(size_t)i * TW + f] = r[1 + f];
     if (threadIdx.x == 0) Jrow[i] = r[0];
+    for (int e = (int)threadIdx.x; e < 9 * NK; e += (int)blockDim.x) {
+        const int x = e / (3 * NK), y = (e / NK) % 3, k = e % NK;
+        double s = 0.0;
+        for (int a = 1; a < Q; ++a) {
+            const int p = mono(k, cvec(a, 0), cvec(a, 1), cvec(a, 2));
+            if (cvec(a, x) == 0 || p == 0) continue;
+            const double S = r[1 + 6 + 3 * a + y] + r[1 + 6 + 3 * opp(a) + y];
+            s += weight(a) * cvec(a, x) * S * p;
+        }
+        tab[(size_t)i * TW + TT + e] = s;
+    }
+}
+
+// lagged force sums of the stored state: lag[pin] = sum_a A+^i_a N_a(q)
+__global__ __launch_bounds__(64) void k_lag3(const Desc3 *__restrict__ dp, int pin)
+{
+    const Desc3 &d = *dp;
+    Cell3 c;
+    if (!cell_of(d, c)) return;
+    const double *tb = d.tab + (size_t)c.i * TW;
+    double L[3] = {0.0, 0.0, 0.0};
+    sfor<1, Q>([&](auto Aic) {
+        constexpr int a = decltype(Aic)::value;
+        const double v = d.P[pin][pidx3(d.n2, d.pitch, c.i, c.j, a, c.k)];
+        L[0] += tb[6 + 3 * a + 0] * v;
+        L[1] += tb[6 + 3 * a + 1] * v;
+        L[2] += tb[6 + 3 * a + 2] * v;
+    });
+    const size_t lrow = ((size_t)c.i * d.n2 + c.j) * d.pitch + c.k, lpl = (size_t)d.n1 * d.n2 * d.pitch;
+    for (int e = 0; e < 3; ++e) d.lag[pin][e * lpl + lrow] = L[e];
 }
 
 // initial state N = J f^eq(rho0, U = Ut = u0; g^ij) (u0 may be null: rest);
@@ -456,11 +529,12 @@ __global__ __launch_bounds__(64) void k_init3(const Desc3 *__restrict__ dp, cons
     if (u0)
         for (int e = 0; e < 3; ++e) U[e] = u0[cell * 3 + e];
     const double G[6] = {tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]};
-    const EqT3 E = eq_tensors(G, U, U);
+    double K[NK];
+    eq_coeffs(G, U, U, K);
     const double m = d.Jrow[c.i] * rho0;
     sfor<0, Q>([&](auto Aic) {
         constexpr int a = decltype(Aic)::value;
-        d.P[0][pidx3(d.n2, d.pitch, c.i, c.j, a, c.k)] = m * phi_dir<a>(E, U);
+        d.P[0][pidx3(d.n2, d.pitch, c.i, c.j, a, c.k)] = m * phi_poly<a>(K);
     });
     if (c.i < CMAX) {
         d.side[0][sidx3(d.n2, d.pitch, 0, 0, c.i, c.j, c.k)] = m;

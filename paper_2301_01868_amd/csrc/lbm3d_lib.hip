@@ -22,7 +22,7 @@ struct lbm3d_grid {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::vector<void *> allocs;
-    double *P[2] = {nullptr, nullptr}, *side[2] = {nullptr, nullptr};
+    double *P[2] = {nullptr, nullptr}, *side[2] = {nullptr, nullptr}, *lag[2] = {nullptr, nullptr};
     double *tab = nullptr, *Jrow = nullptr, *geo = nullptr, *mom = nullptr;
     Desc3 h_desc{};
     Desc3 *d_desc = nullptr;
@@ -138,12 +138,14 @@ int lbm3d_grid_create(const lbm3d_grid_desc *desc, lbm3d_grid **out)
     int *flag = (int *)dalloc3(g, 2 * sizeof(int));
     g->d_desc = (Desc3 *)dalloc3(g, sizeof(Desc3));
     const size_t pe = (size_t)g->n1 * g->n2 * Q * g->pitch, se = (size_t)2 * 3 * CMAX * g->n2 * g->pitch;
+    const size_t le = (size_t)3 * g->n1 * g->n2 * g->pitch;
     for (int b = 0; b < 2; ++b) {
         g->P[b] = (double *)dalloc3(g, pe * 8);
         g->side[b] = (double *)dalloc3(g, se * 8);
+        g->lag[b] = (double *)dalloc3(g, le * 8);
     }
     if (!X || !Y || !Z || !tg || !g->geo || !g->tab || !g->Jrow || !g->mom || !flag || !g->d_desc || !g->P[0] ||
-        !g->P[1] || !g->side[0] || !g->side[1])
+        !g->P[1] || !g->side[0] || !g->side[1] || !g->lag[0] || !g->lag[1])
         return bail(LBM_ENOMEM, "device allocation failed");
     hipStream_t st = g->stream;
 #define HIPB3(call)                                                                                       \
@@ -173,6 +175,8 @@ int lbm3d_grid_create(const lbm3d_grid_desc *desc, lbm3d_grid **out)
     I.P[1] = g->P[1];
     I.side[0] = g->side[0];
     I.side[1] = g->side[1];
+    I.lag[0] = g->lag[0];
+    I.lag[1] = g->lag[1];
     I.tab = g->tab;
     I.Jrow = g->Jrow;
     I.mom = g->mom;
@@ -222,6 +226,8 @@ int lbm3d_init(lbm3d_grid *g, const double *u0)
     g->step = 0;
     hipLaunchKernelGGL(k_init3, dim3(ntiles3(g)), dim3(64), 0, g->stream, (const Desc3 *)g->d_desc, (const double *)du,
                        g->rho0);
+    // the initial state also serves as N'(q, -1): its lagged force sums
+    hipLaunchKernelGGL(k_lag3, dim3(ntiles3(g)), dim3(64), 0, g->stream, (const Desc3 *)g->d_desc, 0);
     HIP3(g, hipGetLastError());
     HIP3(g, hipStreamSynchronize(g->stream));
     if (du) (void)hipFree(du);
@@ -297,6 +303,8 @@ static int state_io(lbm3d_grid *g, double *P, double *side, int to_device)
     if (P) {
         if (to_device) HIP3(g, hipMemcpyAsync(tmp, P, nP * 8, hipMemcpyHostToDevice, g->stream));
         hipLaunchKernelGGL(k_state3, dim3(ntiles3(g)), dim3(64), 0, g->stream, (const Desc3 *)g->d_desc, g->par, tmp, to_device);
+        if (to_device)
+            hipLaunchKernelGGL(k_lag3, dim3(ntiles3(g)), dim3(64), 0, g->stream, (const Desc3 *)g->d_desc, g->par);
         HIP3(g, hipGetLastError());
         if (!to_device) HIP3(g, hipMemcpyAsync(P, tmp, nP * 8, hipMemcpyDeviceToHost, g->stream));
         HIP3(g, hipStreamSynchronize(g->stream));
