@@ -1,11 +1,14 @@
 """Throughput benchmark of the curvilinear lattice Boltzmann step on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                [--geometry auto|cell|cell_table] [--iterations K] [--no-fp64] [--no-fp16] [--no-3d] [--no-cpu]
+                [--geometry auto|cell|cell_table] [--iterations K] [--no-fp64] [--no-fp16] [--no-3d]
+                [--no-large] [--no-cpu]
 python bench.py --serve [--rate R] [--duration S] [--no-sequential]
 
 FP32 populations give the headline figure; the same workload is then timed
-with FP64 and FP16 populations (reported under "fp64" and "fp16").
+with FP64 and FP16 populations (reported under "fp64" and "fp16"), one
+single 4096 x 16384 annulus with FP32 populations (a 5.6 GB buffer, under
+"single_grid_fp32") and the 3D step (under "d3q39_fp64").
 
 A step is one application of the whole fused update (pull streaming with the
 wall sources, moments, lagged inertial force, equilibrium, momentum-flux and
@@ -73,6 +76,8 @@ def workloads():
         "planar_couette_q9_32x16": lambda: [G.workload_planar_couette_q9()],
         # kernel-scaling probe (not one of the stated workloads): the same annulus family at 16x the cells
         "annulus_couette_1024x4096": lambda: [G.workload_annulus_couette(1024, 4096, tau=0.8)],
+        # one HBM-resident grid past 4 GiB per FP32 population buffer (5.6 GB): 67 M cells
+        "annulus_couette_4096x16384": lambda: [G.workload_annulus_couette(4096, 16384, tau=0.8)],
         # general-mapping probe: a sheared, wobbled doubly periodic box whose metric terms depend on
         # q2, so the step rebuilds them per cell from the staged geometry
         "wobbled_box_q21_1024x1024": lambda: [G.periodic_box(21, 1024, 1024, dx=1.0, dy=1.1, skew=0.1, wobble=0.25,
@@ -272,6 +277,7 @@ def main():
     ap.add_argument("--wpb", type=int, default=0)
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D (D3Q39, FP64) leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the single 4096 x 16384 grid leg")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: continuous batching vs sequential FP64 on a Poisson trace")
     ap.add_argument("--rate", type=float, default=50.0)
@@ -355,6 +361,15 @@ def main():
         r16 = measure(cases, lbm.LBM_FP16, args.steps, args.warmup, args.wpb, stream, args.workload, iterations=it,
                       geometry=geom)
 
+    rl = None
+    if not args.no_large and it == 0 and geom == lbm.LBM_GEOM_AUTO:
+        big = "annulus_couette_4096x16384"
+        rl = measure(workloads()[big](), lbm.LBM_FP32, max(8, args.steps // 10), max(2, args.warmup // 10), args.wpb,
+                     stream, big)
+        rl = {"workload": big, "value": round(rl["mlups"], 1), "unit": "MLUPS",
+              "ms_per_step": round(rl["ms_per_step"], 5), "cells": rl["cells"], "roofline": rl["roofline"],
+              "bad_cells_after": rl["bad_cells"]}
+
     r3 = None
     if not args.no_3d and it == 0 and geom == lbm.LBM_GEOM_AUTO:
         r3 = measure3d(max(4, args.steps // 2), max(2, args.warmup // 2), stream)
@@ -392,6 +407,8 @@ def main():
     if r16 is not None:
         out["fp16"] = {"value": round(r16["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r16["ms_per_step"], 5),
                        "roofline": r16["roofline"], "bad_cells_after": r16["bad_cells"]}
+    if rl is not None:
+        out["single_grid_fp32"] = rl
     if r3 is not None:
         out["d3q39_fp64"] = r3
     print(json.dumps(out), flush=True)

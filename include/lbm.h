@@ -167,8 +167,9 @@ int lbm_map_polar(int32_t n1, int32_t n2, int32_t halo, const double *r_faces, i
  * Computes the geometry (tangent basis by central differences, metric,
  * volume J, co-tangents, discrete Christoffel sums) in FP64 on the GPU, builds
  * the step tables and allocates the double-buffered populations.  Errors:
- * LBM_EINVAL (q, sizes: n1 n2 > 2^30 cells, n1 + 2 halo > 65535 or a
- * population buffer of 2 GiB or more; halo < c_max + 1, n1 < c_max with
+ * LBM_EINVAL (q, sizes: n1 n2 > 2^30 cells, n1 + 2 halo > 65535 or rows
+ * so long that 2 c_max + 1 rows of populations reach 4 GiB; halo < c_max + 1,
+ * n1 < c_max with
  * walls, tau <= 1/2, J <= 0 anywhere, unpaired periodic side, unknown
  * precision, offset base, geometry mode or boundary kind), LBM_ENOMEM,
  * LBM_EDEVICE.

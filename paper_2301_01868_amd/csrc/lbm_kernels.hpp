@@ -151,6 +151,19 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t by
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
+// Resource over rows r0 .. r0 + nrows - 1 of a buffer whose rows are
+// row_bytes apart: offsets inside it stay small (32-bit) however large the
+// buffer (the base address carries the row, in 64-bit arithmetic).  The step
+// kernels' WIDE instances address buffers of 2 GiB and more this way; the
+// others keep one resource over the whole buffer (fewer live scalar
+// registers).  r0 may lie outside the buffer (a window that starts above its
+// first row or a periodic wrap shifted by n1 rows): only the accessed rows
+// must exist.
+__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void *base, size_t row_bytes, int r0, int nrows)
+{
+    return make_rsrc((const char *)base + (long long)r0 * (long long)row_bytes, (uint32_t)(row_bytes * (size_t)nrows));
+}
+
 // Cache policy of the population and force-sum accesses: non-temporal (nt)
 // loads and stores (each value is touched once per step; measured faster
 // than the default policy on gfx950).
@@ -579,7 +592,7 @@ struct TabSel<Q, T, 2> {
 // Pulled populations N_a(i, j) of Eq. (adv) with the boundary sources of
 // App. B, read from the post-collision field in HBM and moved to the cell's
 // compute base.  j0 is the first column of the wave's 64.
-template <int Q, typename T, typename S, int CT, typename TBT>
+template <int Q, typename T, typename S, int CT, bool WIDE, typename TBT>
 __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const TBT &tb, int i, int j, int j0, int pin,
                                           T (&n)[Q])
 {
@@ -591,8 +604,9 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
     const long long plane = d->plane;
     const int bclo = d->bc_lo, bchi = d->bc_hi, per1 = d->periodic1;
     constexpr uint32_t ES = sizeof(S);
-    const uint32_t sa_b = (uint32_t)d->sa * ES, sr_b = (uint32_t)d->sr * ES, sb_b = (uint32_t)d->sb * ES;
-    const __amdgpu_buffer_rsrc_t rin = make_rsrc(d->P[pin], (uint32_t)(plane * Q) * ES);
+    const uint32_t sa_b = (uint32_t)d->sa * ES, sb_b = (uint32_t)d->sb * ES;
+    const size_t row_b = (size_t)d->sr * ES;
+    const uint32_t sr_b = (uint32_t)row_b;
     const int bs = d->bs, bm = d->bm;
     const int lane = j - j0;
     // byte offset of the wave's own cells inside a row
@@ -601,6 +615,11 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
     const bool interior = (i >= CM && i < n1 - CM);
     const bool nowrap = (j0 >= CM) && (j0 + 63 + CM < n2);
     if (interior && nowrap) {
+        // one resource over the whole buffer, or (WIDE) over the stencil's
+        // rows i - c_max .. i + c_max; r0 is row i inside it
+        const __amdgpu_buffer_rsrc_t rin = WIDE ? row_rsrc(d->P[pin], row_b, i - CM, 2 * CM + 1)
+                                                : make_rsrc(d->P[pin], (uint32_t)(plane * Q) * ES);
+        const int r0 = WIDE ? CM : i;
         // the whole stencil of the wave stays inside: source (i - c1, j - c2),
         // same direction
         if constexpr (sizeof(S) >= 4) {
@@ -618,7 +637,7 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
             const uint32_t blk = (uint32_t)((j0 >> 6) - 1) * sb_b;
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
-                const uint32_t soff = (uint32_t)a * sa_b + (uint32_t)(i - cx(a)) * sr_b + blk;
+                const uint32_t soff = (uint32_t)a * sa_b + (uint32_t)(r0 - cx(a)) * sr_b + blk;
                 n[a] = pload<Q, S, T>(rin, vsh[cy(a) + CM], soff, a);
                 // to this cell's compute base (the rest direction pulls from the cell itself)
                 if constexpr (CT == 0) n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
@@ -627,7 +646,7 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
             // one block per row (FP16): the column shift rides in the scalar offset
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
-                const uint32_t soff = (uint32_t)((int)(a * sa_b + (i - cx(a)) * sr_b) - cy(a) * (int)ES);
+                const uint32_t soff = (uint32_t)((int)(a * sa_b + (r0 - cx(a)) * sr_b) - cy(a) * (int)ES);
                 n[a] = pload<Q, S, T>(rin, jb, soff, a);
                 // to this cell's compute base (the rest direction pulls from the cell itself)
                 if constexpr (CT == 0) n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
@@ -645,13 +664,27 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
             colb[k + CM] = (uint32_t)(c >> bs) * sb_b + (uint32_t)(c & bm) * ES;
         }
         const T *side_in = (const T *)d->side[pin];
+        // WIDE: every source row lies in the window i - c_max .. i + c_max
+        // (mirror rows at a wall included) or, for a periodic q1, in that
+        // window shifted by +-n1 rows: three resources over 2 c_max + 1 rows
+        // each (rows of a window outside the buffer are never accessed).
+        // Otherwise one resource over the whole buffer.
+        const __amdgpu_buffer_rsrc_t rw = WIDE ? row_rsrc(d->P[pin], row_b, i - CM, 2 * CM + 1)
+                                               : make_rsrc(d->P[pin], (uint32_t)(plane * Q) * ES);
+        const __amdgpu_buffer_rsrc_t rwlo = WIDE ? row_rsrc(d->P[pin], row_b, i - CM + n1, 2 * CM + 1) : rw;
+        const __amdgpu_buffer_rsrc_t rwhi = WIDE ? row_rsrc(d->P[pin], row_b, i - CM - n1, 2 * CM + 1) : rw;
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
             const int c2 = cy(a);
             int r, beta, wall;
             pull_source(i, a, n1, per1, bclo, bchi, r, beta, wall);
             const uint32_t cb = colb[c2 + CM];
-            T v = pload<Q, S, T>(rin, cb, (uint32_t)beta * sa_b + (uint32_t)r * sr_b, a);
+            const int ti = i - cx(a);
+            const bool wlo = WIDE && per1 && ti < 0, whi = WIDE && per1 && ti >= n1;
+            // row inside its resource (a wrapped row sits in its window where
+            // the unwrapped one would)
+            const uint32_t rrel = WIDE ? (uint32_t)((wlo || whi ? ti : r) - (i - CM)) : (uint32_t)r;
+            T v = pload<Q, S, T>(wlo ? rwlo : (whi ? rwhi : rw), cb, (uint32_t)beta * sa_b + rrel * sr_b, a);
             if constexpr (CT == 0) v += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             if (c2 != 0 && wall != 0) {
                 const int sd = wall - 1;
@@ -857,21 +890,22 @@ __device__ __forceinline__ void project_update(const T (&n)[Q], T (&s)[Q], T JF1
 // and encoded), with LAGW the lagged force sums the next step of the
 // lag-buffer kernels reads, and the moving walls' side state: m and Ut^2 of
 // the rows a wall pulls from (App. B.3).
-template <int Q, typename T, typename S, int CT, bool LAGW, typename TBT>
+template <int Q, typename T, typename S, int CT, bool LAGW, bool WIDE, typename TBT>
 __device__ __forceinline__ void store_cell(const InstDesc *__restrict__ d, const TBT &tb, int i, int j, int pin,
                                            const T (&s)[Q], const CellOut<T> &o)
 {
     using TB = Tab<Q>;
     constexpr uint32_t ES = sizeof(S);
-    const long long plane = d->plane;
-    const uint32_t sa_b = (uint32_t)d->sa * ES, sr_b = (uint32_t)d->sr * ES, sb_b = (uint32_t)d->sb * ES;
+    const uint32_t sa_b = (uint32_t)d->sa * ES, sb_b = (uint32_t)d->sb * ES;
     const uint32_t jb = (uint32_t)(j >> d->bs) * sb_b + (uint32_t)(j & d->bm) * ES;
-    const __amdgpu_buffer_rsrc_t rout = make_rsrc(d->P[pin ^ 1], (uint32_t)(plane * Q) * ES);
+    const __amdgpu_buffer_rsrc_t rout = WIDE ? row_rsrc(d->P[pin ^ 1], (size_t)d->sr * ES, i, 1)
+                                             : make_rsrc(d->P[pin ^ 1], (uint32_t)(d->plane * Q) * ES);
+    const uint32_t rowb = WIDE ? 0u : (uint32_t)i * (uint32_t)d->sr * ES;
     T Lx1 = 0, Lx2 = 0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         const T st = s[a] + tb(TB::SB(a));                                  // storage base
-        pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + (uint32_t)i * sr_b, a, st);
+        pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + rowb, a, st);
         if constexpr (LAGW) {
             const T v = pdec<Q, S, T>(penc<Q, S, T>(st, a), a) - tb(TB::SB(a));  // as stored, compute base
             if (a > 0) {
@@ -883,9 +917,11 @@ __device__ __forceinline__ void store_cell(const InstDesc *__restrict__ d, const
     }
     if constexpr (LAGW) {
         constexpr uint32_t ET = sizeof(T);
-        const uint32_t lag_bytes = 2 * (uint32_t)plane * ET, lsa_b = (uint32_t)d->lsa * ET;
-        const uint32_t jt = (uint32_t)j * ET, rowt = (uint32_t)i * (uint32_t)d->lsr * ET;
-        const __amdgpu_buffer_rsrc_t rlago = make_rsrc(d->lag[pin ^ 1], lag_bytes);
+        const uint32_t lsa_b = (uint32_t)d->lsa * ET;
+        const uint32_t jt = (uint32_t)j * ET;
+        const __amdgpu_buffer_rsrc_t rlago = WIDE ? row_rsrc(d->lag[pin ^ 1], (size_t)d->lsr * ET, i, 1)
+                                                  : make_rsrc(d->lag[pin ^ 1], 2 * (uint32_t)d->plane * ET);
+        const uint32_t rowt = WIDE ? 0u : (uint32_t)i * (uint32_t)d->lsr * ET;
         bstore<T, T>(rlago, jt, rowt, Lx1);
         bstore<T, T>(rlago, jt, lsa_b + rowt, Lx2);
     }
@@ -905,20 +941,22 @@ __device__ __forceinline__ void store_cell(const InstDesc *__restrict__ d, const
 // Lagged own-cell force sums sum_a A+^i_a s_a(q, t - 1) from the own cell's
 // stored post-collision values (the sums the lag-buffer kernels store, formed
 // in the same order, so bitwise the same)
-template <int Q, typename T, typename S, typename TBT>
+template <int Q, typename T, typename S, bool WIDE, typename TBT>
 __device__ __forceinline__ void own_lag_global(const InstDesc *__restrict__ d, const TBT &tb, int i, int j, int pin,
                                                T &Lo1, T &Lo2)
 {
     using TB = Tab<Q>;
     constexpr uint32_t ES = sizeof(S);
-    const uint32_t sa_b = (uint32_t)d->sa * ES, sr_b = (uint32_t)d->sr * ES, sb_b = (uint32_t)d->sb * ES;
+    const uint32_t sa_b = (uint32_t)d->sa * ES, sb_b = (uint32_t)d->sb * ES;
     const uint32_t jb = (uint32_t)(j >> d->bs) * sb_b + (uint32_t)(j & d->bm) * ES;
-    const __amdgpu_buffer_rsrc_t rin = make_rsrc(d->P[pin], (uint32_t)(d->plane * Q) * ES);
+    const __amdgpu_buffer_rsrc_t rin = WIDE ? row_rsrc(d->P[pin], (size_t)d->sr * ES, i, 1)
+                                            : make_rsrc(d->P[pin], (uint32_t)(d->plane * Q) * ES);
+    const uint32_t rowb = WIDE ? 0u : (uint32_t)i * (uint32_t)d->sr * ES;
     Lo1 = 0;
     Lo2 = 0;
 #pragma unroll
     for (int a = 1; a < Q; ++a) {
-        const T v = pload<Q, S, T>(rin, jb, (uint32_t)a * sa_b + (uint32_t)i * sr_b, a) - tb(TB::SB(a));
+        const T v = pload<Q, S, T>(rin, jb, (uint32_t)a * sa_b + rowb, a) - tb(TB::SB(a));
         Lo1 += tb(TB::A1(a)) * v;
         Lo2 += tb(TB::A2(a)) * v;
     }
@@ -931,7 +969,7 @@ __device__ __forceinline__ void own_lag_global(const InstDesc *__restrict__ d, c
 // instead of colliding (for per-row tables it forms the lagged sums from the
 // own cell's stored values, which serves grids stepped by either kernel).
 // ---------------------------------------------------------------------------
-template <int Q, typename T, typename S, int CT, bool MOM, bool ITER>
+template <int Q, typename T, typename S, int CT, bool MOM, bool ITER, bool WIDE>
 __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, const int4 tl, int par)
 {
     using TB = Tab<Q>;
@@ -963,18 +1001,19 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
     }
 
     T n[Q], s[Q];
-    pull_cell<Q, T, S, CT>(d, tb, i, j, j0, pin, n);
+    pull_cell<Q, T, S, CT, WIDE>(d, tb, i, j, j0, pin, n);
 
     T Lo1, Lo2;
     if constexpr (MOM && CT == 0) {
-        own_lag_global<Q, T, S>(d, tb, i, j, pin, Lo1, Lo2);
+        own_lag_global<Q, T, S, WIDE>(d, tb, i, j, pin, Lo1, Lo2);
     } else {
         // lagged own-cell force sums, formed when the previous step produced
         // N'(q, t-1)
         constexpr uint32_t ET = sizeof(T);
-        const uint32_t lag_bytes = 2 * (uint32_t)d->plane * ET, lsa_b = (uint32_t)d->lsa * ET;
-        const __amdgpu_buffer_rsrc_t rlag = make_rsrc(d->lag[pin], lag_bytes);
-        const uint32_t jt = (uint32_t)j * ET, rowt = (uint32_t)i * (uint32_t)d->lsr * ET;
+        const uint32_t lsa_b = (uint32_t)d->lsa * ET;
+        const __amdgpu_buffer_rsrc_t rlag = WIDE ? row_rsrc(d->lag[pin], (size_t)d->lsr * ET, i, 1)
+                                                 : make_rsrc(d->lag[pin], 2 * (uint32_t)d->plane * ET);
+        const uint32_t jt = (uint32_t)j * ET, rowt = WIDE ? 0u : (uint32_t)i * (uint32_t)d->lsr * ET;
         Lo1 = bload<T, T>(rlag, jt, rowt);
         Lo2 = bload<T, T>(rlag, jt, lsa_b + rowt);
     }
@@ -996,17 +1035,18 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
         mo[3 * nc + c] = (double)o.Ut1;
         mo[4 * nc + c] = (double)o.Ut2;
     } else {
-        store_cell<Q, T, S, CT, true>(d, tb, i, j, pin, s, o);
+        store_cell<Q, T, S, CT, true, WIDE>(d, tb, i, j, pin, s, o);
     }
 }
 
 // One tile (row segment of 64 columns per wave) per workgroup.  The tile
-// table holds (instance, first row, first column, lattice).
-template <int Q, typename T, typename S, int CT, bool MOM, bool ITER>
+// table holds (instance, first row, first column, lattice).  WIDE instances
+// serve population buffers of 2 GiB and more.
+template <int Q, typename T, typename S, int CT, bool MOM, bool ITER, bool WIDE>
 __global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts, const int4 *__restrict__ tiles,
                                               int par)
 {
-    step_tile<Q, T, S, CT, MOM, ITER>(insts, tiles[blockIdx.x], par);
+    step_tile<Q, T, S, CT, MOM, ITER, WIDE>(insts, tiles[blockIdx.x], par);
 }
 
 // D2Q9 and D2Q21 tiles in one launch: the lattice is the tile's fourth field
@@ -1017,9 +1057,9 @@ __global__ __launch_bounds__(256) void k_step_mixed(const InstDesc *__restrict__
 {
     const int4 tl = tiles[blockIdx.x];
     if (tl.w == 9)
-        step_tile<9, T, S, CT, MOM, ITER>(insts, tl, par);
+        step_tile<9, T, S, CT, MOM, ITER, false>(insts, tl, par);
     else
-        step_tile<21, T, S, CT, MOM, ITER>(insts, tl, par);
+        step_tile<21, T, S, CT, MOM, ITER, false>(insts, tl, par);
 }
 
 } // namespace lbm

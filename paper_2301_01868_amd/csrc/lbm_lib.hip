@@ -32,6 +32,7 @@ struct lbm_grid {
     int q = 0, n1 = 0, n2 = 0, h = 0, pitch = 0, hw = 0, ncell = 0;
     int row = 1, nent = 0;
     int ct = 0;                   // step tables: 0 per row, 1 per cell, 2 per cell rebuilt from the geometry
+    int wide = 0;                 // a population buffer of 2 GiB or more: the step's row-based addressing
     double *ge = nullptr;         // staged geometry of ct = 2 (GE_* fields)
     int precision = LBM_FP64;
     int device = 0;               // device current at create (the grid's buffers live there)
@@ -74,7 +75,7 @@ struct lbm_batch {
     hipEvent_t ev = nullptr;
     double *d_res = nullptr;           // [grids][RED_NF] reduction results
     struct Group {
-        int q = 0, precision = 0, cell = 0, iter = 0;
+        int q = 0, precision = 0, cell = 0, iter = 0, wide = 0;
         InstDesc *d_inst = nullptr;
         int4 *d_tiles = nullptr;
         int ntiles = 0, wpb = 4, cap = 0;
@@ -160,25 +161,30 @@ static unsigned occupancy_lds(int cap, int wpb)
 // kernel dispatch tables -------------------------------------------------------
 typedef void (*StepFn)(const InstDesc *, const int4 *, int);
 
-template <int Q, int CT, bool MOM, bool ITER>
-static StepFn step_fn3(int precision)
+template <int Q, int CT, bool MOM, bool ITER, bool WIDE>
+static StepFn step_fn4(int precision)
 {
-    if (precision == LBM_FP64) return k_step<Q, double, double, CT, MOM, ITER>;
-    if (precision == LBM_FP16) return k_step<Q, float, _Float16, CT, MOM, ITER>;
-    return k_step<Q, float, float, CT, MOM, ITER>;
+    if (precision == LBM_FP64) return k_step<Q, double, double, CT, MOM, ITER, WIDE>;
+    if (precision == LBM_FP16) return k_step<Q, float, _Float16, CT, MOM, ITER, WIDE>;
+    return k_step<Q, float, float, CT, MOM, ITER, WIDE>;
+}
+template <int Q, int CT, bool MOM, bool ITER>
+static StepFn step_fn3(int precision, int wide)
+{
+    return wide ? step_fn4<Q, CT, MOM, ITER, true>(precision) : step_fn4<Q, CT, MOM, ITER, false>(precision);
 }
 
 // the moments pass reads the stored tables (per-cell tables exist for every
 // per-cell grid)
 template <int Q>
-static StepFn step_fn(int precision, int ct, int mom, int iter)
+static StepFn step_fn(int precision, int ct, int mom, int iter, int wide)
 {
-    if (mom) return ct ? step_fn3<Q, 1, true, false>(precision) : step_fn3<Q, 0, true, false>(precision);
+    if (mom) return ct ? step_fn3<Q, 1, true, false>(precision, wide) : step_fn3<Q, 0, true, false>(precision, wide);
     if (iter)
-        return ct == 2 ? step_fn3<Q, 2, false, true>(precision)
-                       : (ct ? step_fn3<Q, 1, false, true>(precision) : step_fn3<Q, 0, false, true>(precision));
-    return ct == 2 ? step_fn3<Q, 2, false, false>(precision)
-                   : (ct ? step_fn3<Q, 1, false, false>(precision) : step_fn3<Q, 0, false, false>(precision));
+        return ct == 2 ? step_fn3<Q, 2, false, true>(precision, wide)
+                       : (ct ? step_fn3<Q, 1, false, true>(precision, wide) : step_fn3<Q, 0, false, true>(precision, wide));
+    return ct == 2 ? step_fn3<Q, 2, false, false>(precision, wide)
+                   : (ct ? step_fn3<Q, 1, false, false>(precision, wide) : step_fn3<Q, 0, false, false>(precision, wide));
 }
 
 // kernel for a grid or batch group: lattice, storage precision, table kind,
@@ -191,14 +197,15 @@ static StepFn mixed_fn(int precision)
     return k_step_mixed<float, float, CT, false, ITER>;
 }
 
-// q = 0: a batch group holding both lattices (one fused launch, no moments pass)
-static StepFn pick_step(int q, int precision, int ct, int mom, int iter)
+// q = 0: a batch group holding both lattices (one fused launch, no moments
+// pass; its grids are never wide)
+static StepFn pick_step(int q, int precision, int ct, int mom, int iter, int wide)
 {
     if (q == 0) {
         if (iter) return ct == 2 ? mixed_fn<2, true>(precision) : (ct ? mixed_fn<1, true>(precision) : mixed_fn<0, true>(precision));
         return ct == 2 ? mixed_fn<2, false>(precision) : (ct ? mixed_fn<1, false>(precision) : mixed_fn<0, false>(precision));
     }
-    return q == 9 ? step_fn<9>(precision, ct, mom, iter) : step_fn<21>(precision, ct, mom, iter);
+    return q == 9 ? step_fn<9>(precision, ct, mom, iter, wide) : step_fn<21>(precision, ct, mom, iter, wide);
 }
 
 // dynamic LDS of a step launch: the occupancy reservation, or the staged
@@ -277,7 +284,7 @@ static int build_tiles(lbm_grid *g)
 
 static int launch_step(lbm_grid *g, int par, int mom)
 {
-    StepFn fn = pick_step(g->q, g->precision, g->ct, mom, g->h_inst.iters > 0);
+    StepFn fn = pick_step(g->q, g->precision, g->ct, mom, g->h_inst.iters > 0, g->wide);
     hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), step_lds(g->ct, g->q, g->precision, g->cap, g->wpb), g->stream, (const InstDesc *)g->d_inst,
                        (const int4 *)g->d_tiles, par);
     HIPCHK(g, hipGetLastError());
@@ -373,10 +380,12 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     // the set-up kernels launch one grid row of threads per mapping row
     if ((int64_t)D.n1 + 2 * (int64_t)D.halo > 65535)
         return fail(nullptr, LBM_EINVAL, "n1 + 2 halo must not exceed 65535");
-    {   // one population buffer must stay below 2 GiB (32-bit buffer offsets)
+    {   // the step addresses populations through resources based at a row: the
+        // 2 c_max + 1 rows of a stencil must stay below 4 GiB (32-bit offsets)
         const int64_t pitch = D.n2 >= 64 ? (D.n2 + 63) / 64 * 64 : D.n2;
-        if ((int64_t)D.q * D.n1 * pitch * (D.precision == LBM_FP64 ? 8 : 4) >= ((int64_t)1 << 31))
-            return fail(nullptr, LBM_EINVAL, "grid too large for one population buffer (2 GiB)");
+        const int64_t row_bytes = (int64_t)D.q * pitch * (D.precision == LBM_FP64 ? 8 : (D.precision == LBM_FP16 ? 2 : 4));
+        if ((2 * cm + 1) * row_bytes >= ((int64_t)1 << 32))
+            return fail(nullptr, LBM_EINVAL, "rows too long: 2 c_max + 1 rows of populations must stay below 4 GiB");
     }
 
     lbm_grid *g = new lbm_grid();
@@ -531,6 +540,7 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
 
     // populations and side state
     const size_t plane = (size_t)n1 * g->pitch;
+    g->wide = plane * q * store_size(g->precision) >= ((size_t)1 << 31) ? 1 : 0;
     for (int b = 0; b < 2; ++b) {
         g->P[b] = dalloc(g, plane * q * store_size(g->precision));
         g->side[b] = dalloc(g, (size_t)4 * g->hw * g->pitch * comp_size(g->precision));
@@ -790,7 +800,7 @@ static int capture_graph(lbm_grid *g, int start_par, int steps)
     HIPCHK(g, hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
     int par = start_par;
     for (int s = 0; s < steps; ++s) {
-        StepFn fn = pick_step(g->q, g->precision, g->ct, 0, g->h_inst.iters > 0);
+        StepFn fn = pick_step(g->q, g->precision, g->ct, 0, g->h_inst.iters > 0, g->wide);
         hipLaunchKernelGGL(fn, dim3(g->ntiles), dim3(64 * g->wpb), step_lds(g->ct, g->q, g->precision, g->cap, g->wpb), g->stream, (const InstDesc *)g->d_inst,
                            (const int4 *)g->d_tiles, par);
         par ^= 1;
@@ -1332,7 +1342,7 @@ int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_b
     *out = nullptr;
     lbm_batch *b = new lbm_batch();
     b->stream = grids[0]->stream;
-    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
     for (int k = 0; k < n; ++k) {
         lbm_grid *g = grids[k];
         if (!g || !g->inited) {
@@ -1346,7 +1356,9 @@ int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_b
         if (g->stream != b->stream && std::find(b->others.begin(), b->others.end(), g->stream) == b->others.end())
             b->others.push_back(g->stream);
         b->grids.push_back(g);
-        groups[std::make_tuple(fuse ? 0 : g->q, g->precision, g->ct, g->h_inst.iters > 0 ? 1 : 0)].push_back(k);
+        // wide grids keep their lattice's kernel (the fused one addresses whole buffers)
+        groups[std::make_tuple(fuse && !g->wide ? 0 : g->q, g->precision, g->ct, g->h_inst.iters > 0 ? 1 : 0, g->wide)]
+            .push_back(k);
     }
     for (auto &kv : groups) {
         lbm_batch::Group G;
@@ -1357,6 +1369,7 @@ int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_b
         G.precision = std::get<1>(kv.first);
         G.cell = std::get<2>(kv.first);
         G.iter = std::get<3>(kv.first);
+        G.wide = std::get<4>(kv.first);
         G.wpb = b->grids[kv.second[0]]->wpb;
         G.cap = b->grids[kv.second[0]]->cap;
         G.members = kv.second;
@@ -1417,7 +1430,7 @@ static int batch_join_out(lbm_batch *b)
 static int batch_launch(lbm_batch *b, int par)
 {
     for (auto &G : b->groups) {
-        StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter);
+        StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter, G.wide);
         hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), step_lds(G.cell, G.q, G.precision, G.cap, G.wpb), b->stream, (const InstDesc *)G.d_inst,
                            (const int4 *)G.d_tiles, par);
     }
@@ -1502,10 +1515,7 @@ int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *preci
     if (precision) *precision = G.precision;
     if (cells) {
         int64_t c = 0;
-        for (lbm_grid *g : b->grids)
-            if ((G.q == 0 || g->q == G.q) && g->precision == G.precision && g->ct == G.cell &&
-                (g->h_inst.iters > 0 ? 1 : 0) == G.iter)
-                c += g->ncell;
+        for (int k : G.members) c += b->grids[k]->ncell;
         *cells = c;
     }
     return (int)b->groups.size();
@@ -1517,7 +1527,7 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n)
         return fail(nullptr, LBM_EINVAL, "bad group step arguments (n must be even)");
     if (const int u = batch_usable(b)) return u;
     const auto &G = b->groups[group];
-    StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter);
+    StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter, G.wide);
     for (int64_t k = 0; k < n; ++k)
         hipLaunchKernelGGL(fn, dim3(G.ntiles), dim3(64 * G.wpb), step_lds(G.cell, G.q, G.precision, G.cap, G.wpb), b->stream, (const InstDesc *)G.d_inst,
                            (const int4 *)G.d_tiles, (int)((b->step + k) & 1));
@@ -1556,7 +1566,7 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps)
                 return rc;
             }
         }
-        StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter);
+        StepFn fn = pick_step(G.q, G.precision, G.cell, 0, G.iter, G.wide);
         int best_s = 0, best_c = 0;
         float best_ms = 1e30f;
         int64_t k = b->step;            // this group's grids are at the batch's time level

@@ -88,8 +88,10 @@ def one_step_sampled(g, case, nsample=1500, seed=0, iterations=0):
     o = oracle.OracleGrid(case)
     o.set_iterations(iterations)
     o.set_state(to_oracle_state(P0))
+    del P0
     m_s, u_s = side_to_oracle(side0, case.n1, case.n2)
     o.set_side(np.nan_to_num(m_s), np.nan_to_num(u_s))
+    del m_s, u_s
     rng = np.random.default_rng(seed)
     # every wall-adjacent row plus random interior cells
     rows = list(range(min(4, case.n1))) + list(range(max(0, case.n1 - 4), case.n1))
@@ -97,7 +99,8 @@ def one_step_sampled(g, case, nsample=1500, seed=0, iterations=0):
     cells += list(rng.choice(case.ncell, nsample, replace=False))
     cells = np.array(sorted(set(cells)), dtype=np.int32)
     ref = o.step_cells(cells)
+    del o
     g.step(1)
     P1, _ = g.get_state()
-    got = to_oracle_state(P1)[cells]
+    got = P1.reshape(P1.shape[0], -1)[:, cells].T
     return np.abs(got - ref).max() / np.abs(ref).max()

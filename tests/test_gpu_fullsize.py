@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import one_step_sampled as _one_step_sampled, say
+from gpu_util import initial_velocity, one_step_sampled as _one_step_sampled, say
 from paper_2301_01868_amd import grids as G
 from paper_2301_01868_amd import lbm
 
@@ -198,27 +198,36 @@ def _channel(n1, n2):
     return G.planar_couette(21, G.faces_uniform(n1), n2=n2, u_wall=0.05, tau=0.8)
 
 
-# FP64 on the exactly representable channel: on an annulus of this size (R2 = 2048 mean radial
-# steps) the two FP64 implementations' metric terms already differ at the 1e-12 level, since each
-# forms them from coordinates of magnitude R2 by differences over unit steps
-@pytest.mark.parametrize("prec,make,n1,n2,tol1", [(lbm.LBM_FP32, _annulus, 2048, 12480, 3e-6),
-                                                  (lbm.LBM_FP64, _channel, 1024, 12480, 1e-13)],
-                         ids=["fp32_annulus", "fp64_channel"])
-def test_largest_accepted_grid(prec, make, n1, n2, tol1):
-    """The largest population buffer the library accepts: 21 x n1 x pitch
-    values just under 2 GiB (2,146,959,360 bytes), the reach of the step's
-    32-bit buffer offsets.  One step from a sheared state against the oracle
-    on sampled cells (every wall-adjacent row, so the buffer's last rows too);
-    one more column block is rejected at create."""
+# Single grids past 4 GiB per population buffer.  FP64 runs on the exactly
+# representable channel: on an annulus of this size the two FP64
+# implementations' metric terms already differ at the 1e-12 level, since each
+# forms them from coordinates of magnitude R2 by differences over unit steps.
+# The last case sits at the row-window limit: 7 FP64 D2Q21 rows of 3,652,160
+# cells are 4,294,940,160 bytes, one more column block crosses 2^32.
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("prec,make,n1,n2,tol1", [(lbm.LBM_FP32, _annulus, 4096, 16384, 3e-6),
+                                                  (lbm.LBM_FP64, _channel, 2048, 16384, 1e-13),
+                                                  (lbm.LBM_FP64, _channel, 7, 3_652_160, 1e-13)],
+                         ids=["fp32_annulus_4096x16384", "fp64_channel_2048x16384", "fp64_row_window_limit"])
+def test_large_single_grid(prec, make, n1, n2, tol1):
+    """One grid whose population buffers exceed the 4 GiB reach of a 32-bit
+    buffer offset (5.6 GB each for the first two cases): the step addresses
+    them through resources based at the stencil's first row.  One step from a
+    sheared state against the oracle on sampled cells (every wall-adjacent row,
+    so the buffer's last rows too)."""
     case = make(n1, n2)
-    say("largest grid", case.meta["problem"], n1, "x", n2, "prec", prec)
+    say("large grid", case.meta["problem"], n1, "x", n2, "prec", prec)
     s = 8 if prec == lbm.LBM_FP64 else 4
-    assert 21 * n1 * n2 * s == 2_146_959_360 < 2 ** 31
-    bigger = make(n1, n2 + 1)
-    with pytest.raises(lbm.LbmError) as e:
-        lbm.Grid(bigger, precision=prec)
-    assert e.value.code == lbm.LBM_EINVAL
-    del bigger
+    pitch = (n2 + 63) // 64 * 64
+    assert 21 * 7 * pitch * s < 2 ** 32
+    if n1 == 7:
+        bigger = make(n1, n2 + 1)
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.Grid(bigger, precision=prec)
+        assert e.value.code == lbm.LBM_EINVAL and "rows too long" in str(e.value)
+        del bigger
+    else:
+        assert 21 * n1 * pitch * s > 2 ** 32
     g = lbm.Grid(case, precision=prec)
     assert g.info.row_tables == 1
     i = (np.arange(n1)[:, None] + 0.5) / n1
@@ -230,7 +239,45 @@ def test_largest_accepted_grid(prec, make, n1, n2, tol1):
     g.step(3)
     r = g.residual(check=False)
     assert r.bad_cells == 0
+    say("large grid stepped; oracle one-step on sampled cells")
     e1 = _one_step_sampled(g, case, nsample=3000)
-    say("largest grid one-step sampled rel err", e1)
+    say("large grid one-step sampled rel err", e1)
     assert e1 <= tol1
+    g.close()
+
+
+@pytest.mark.timeout(1200)
+def test_wide_periodic_box_in_a_fused_batch():
+    """A doubly periodic, wobbled box whose FP32 population buffer passes
+    2 GiB (21 x 1600 x 16384 x 4 bytes), so the step addresses it row by row:
+    periodic q1 wraps (rows shifted by n1), per-cell tables.  In a batch asked
+    to fuse lattices it keeps a group of its own beside a small D2Q9 grid;
+    after batch steps, one step against the oracle on sampled cells."""
+    case = G.periodic_box(21, 1600, 16384, wobble=0.3, tau=0.8)
+    say("wide periodic box", case.n1, "x", case.n2)
+    assert 21 * case.n1 * case.n2 * 4 >= 2 ** 31
+    g = lbm.Grid(case, precision=lbm.LBM_FP32)
+    assert g.info.row_tables == 0
+    u0 = initial_velocity(case)
+    g.init(u0)
+    del u0
+    small_case = G.periodic_box(9, 64, 96, wobble=0.2, tau=0.9)
+    small = lbm.Grid(small_case, precision=lbm.LBM_FP32)
+    small.init(initial_velocity(small_case))
+    alone = lbm.Grid(small_case, precision=lbm.LBM_FP32)
+    alone.init(initial_velocity(small_case))
+    b = lbm.lbm_batch_create_ex([g.h, small.h], lbm.LBM_BATCH_FUSE_LATTICES)
+    groups = lbm.lbm_batch_groups(b)
+    say("groups", groups)
+    assert sorted((q, cells) for q, _, cells in groups) == [(9, small_case.ncell), (21, case.ncell)]
+    lbm.lbm_batch_step(b, 4)
+    lbm.lbm_batch_destroy(b)
+    alone.step(4)
+    assert np.array_equal(alone.get_state()[0], small.get_state()[0])
+    r = g.residual(check=False)
+    assert r.bad_cells == 0
+    say("wide box batch-stepped; oracle one-step on sampled cells")
+    e1 = _one_step_sampled(g, case, nsample=3000)
+    say("wide box one-step sampled rel err", e1)
+    assert e1 <= 3e-6
     g.close()
