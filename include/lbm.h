@@ -294,6 +294,14 @@ int lbm_geometry(lbm_grid *g, double *out);
 int lbm_synchronize(lbm_grid *g);
 void *lbm_stream(lbm_grid *g);
 
+/* Move all later work of grid g to `stream` (a hipStream_t of the grid's
+ * device; NULL: a stream the library makes and owns).  Work already queued on
+ * the old stream stays ordered before it (an event wait; a stream the library
+ * owned is then destroyed, which waits for that work).  Lets a caller create
+ * and initialise a grid on a setup stream while other work runs, then hand it
+ * to the stream its batch runs on.  LBM_ESTATE while a batch holds the grid. */
+int lbm_grid_set_stream(lbm_grid *g, void *stream);
+
 /* Many grids advanced together: one launch per group of grids sharing lattice,
  * precision, table kind and force mode (lagged, or fixed-point passes) per step
  * over a flattened table of row tiles; steps of a batch are captured in HIP
@@ -320,6 +328,22 @@ int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_b
 int lbm_batch_step(lbm_batch *b, int64_t n);
 void lbm_batch_destroy(lbm_batch *b);
 
+/* Continuous batching: make grids[0..n-1] the batch's members (n >= 0; the
+ * same rules as lbm_batch_create for each grid; grids may join at any step
+ * count, each keeps its own buffer parity).  Waits for the batch's queued
+ * steps, then rewrites the groups' instance and tile tables in place (a table
+ * grows, to twice its size or more, only when the new one does not fit) and,
+ * when every group keeps its step kernel, updates the kernel nodes of the
+ * batch's instantiated step graph in place (new tile counts and tables)
+ * instead of building a new graph.  Grids that leave may then be stepped
+ * alone or destroyed.  The batch keeps its stream, unless that stream is
+ * owned by a grid that leaves: then the batch moves, in stream order, to the
+ * first remaining grid's stream (or to one of its own).  With n = 0 the
+ * batch is empty and lbm_batch_step only counts steps.  Errors in the grids
+ * leave the batch as it was; an allocation or device error leaves it broken
+ * (LBM_ESTATE from then on). */
+int lbm_batch_update(lbm_batch *b, lbm_grid *const *grids, int32_t n);
+
 /* Residuals of every grid of the batch (out[n], batch order) with one
  * synchronisation; same definitions as lbm_residual.  Returns LBM_EUNSTABLE
  * (after filling every record) if any grid has bad cells. */
@@ -328,7 +352,8 @@ int lbm_batch_residuals(lbm_batch *b, lbm_resid *out);
 /* Group g of a batch (one lattice/precision/table kind/force mode, one kernel launch per
  * step): returns the number of groups (>= 0) or an error; fills the lattice
  * (0 for a fused group holding both lattices), precision and total cells of
- * group g when g is in range. */
+ * group g.  With every output pointer NULL, any g returns the count (an
+ * empty batch has none); otherwise g out of range is LBM_EINVAL. */
 int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *precision, int64_t *cells);
 
 /* Measurement hook: launch only group g's step kernel n times (n even, so

@@ -73,17 +73,29 @@ struct lbm_batch {
     hipStream_t stream = nullptr;
     std::vector<hipStream_t> others;   // distinct grid streams other than `stream`
     hipEvent_t ev = nullptr;
-    double *d_res = nullptr;           // [grids][RED_NF] reduction results
+    uint32_t flags = 0;
+    bool own_stream = false;           // the stream was made for the batch (its members left)
+    double *d_res = nullptr;           // [res_cap][RED_NF] reduction results
+    size_t res_cap = 0;
     struct Group {
         int q = 0, precision = 0, cell = 0, iter = 0, wide = 0;
         InstDesc *d_inst = nullptr;
         int4 *d_tiles = nullptr;
         int ntiles = 0, wpb = 4, cap = 0;
+        int inst_cap = 0, tile_cap = 0; // capacity of d_inst and d_tiles (entries)
         std::vector<int> members;      // indices into grids
     };
     std::vector<Group> groups;
     std::vector<void *> allocs;
-    GraphCache graph;
+    // the step graph: GS steps, one kernel node per group and step, built node
+    // by node so that membership changes can update the nodes in place
+    hipGraph_t gtmpl = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct Node {
+        hipGraphNode_t node;
+        int group, par;
+    };
+    std::vector<Node> nodes;
     int64_t step = 0;
     bool broken = false;               // a member grid was destroyed first: only destroy is allowed
 };
@@ -1274,19 +1286,54 @@ int lbm_synchronize(lbm_grid *g)
 
 void *lbm_stream(lbm_grid *g) { return g ? (void *)g->stream : nullptr; }
 
+int lbm_grid_set_stream(lbm_grid *g, void *stream)
+{
+    if (!g) return fail(nullptr, LBM_EINVAL, "null grid");
+    if (!g->batches.empty()) return fail(g, LBM_ESTATE, "a grid held by a batch keeps its stream");
+    hipStream_t s = (hipStream_t)stream;
+    if (s && s == g->stream) return LBM_OK;
+    bool own = false;
+    if (!s) {
+        if (hipStreamCreate(&s) != hipSuccess) return fail(g, LBM_EDEVICE, "hipStreamCreate failed");
+        own = true;
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, g->stream) != hipSuccess ||
+        hipStreamWaitEvent(s, ev, 0) != hipSuccess) {
+        if (ev) (void)hipEventDestroy(ev);
+        if (own) (void)hipStreamDestroy(s);
+        return fail(g, LBM_EDEVICE, "stream handover failed");
+    }
+    (void)hipEventDestroy(ev);
+    if (g->own_stream) (void)hipStreamDestroy(g->stream);
+    g->stream = s;
+    g->own_stream = own;
+    return LBM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // batches
 // ---------------------------------------------------------------------------
+static void batch_drop_graph(lbm_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->gtmpl) (void)hipGraphDestroy(b->gtmpl);
+    b->gexec = nullptr;
+    b->gtmpl = nullptr;
+    b->nodes.clear();
+}
+
 void lbm_batch_destroy(lbm_batch *b)
 {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     for (hipStream_t s : b->others) (void)hipStreamSynchronize(s);
-    if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
+    batch_drop_graph(b);
     for (void *p : b->allocs) (void)hipFree(p);
     if (b->ev) (void)hipEventDestroy(b->ev);
     for (lbm_grid *g : b->grids)
         if (g) g->batches.erase(std::remove(g->batches.begin(), g->batches.end(), b), g->batches.end());
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
 
@@ -1297,10 +1344,36 @@ static int batch_usable(const lbm_batch *b)
     return LBM_OK;
 }
 
-// Tile table of a batch group for `wpb` rows per workgroup: the members'
-// tiles (instance = position in the group) in the XCD-run order, uploaded
-// to a device allocation the batch owns.
-static int group_tiles(lbm_batch *b, const std::vector<int> &members, int wpb, int4 **d_out, int *nt_out)
+static void batch_free(lbm_batch *b, void *p)
+{
+    auto it = std::find(b->allocs.begin(), b->allocs.end(), p);
+    if (it != b->allocs.end()) b->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+// Copy `count` entries of `each` bytes into the device array *d holding *cap
+// entries; a larger count replaces the array by one of at least twice the
+// capacity (so a changing membership reallocates rarely).
+static int upload_grow(lbm_batch *b, void **d, int *cap, const void *src, size_t count, size_t each)
+{
+    if (!*d || count > (size_t)*cap) {
+        const size_t nc = std::max<size_t>(std::max<size_t>(count, 1), 2 * (size_t)*cap);
+        void *p = nullptr;
+        if (hipMalloc(&p, nc * each) != hipSuccess) return fail(nullptr, LBM_ENOMEM, "batch allocation failed");
+        b->allocs.push_back(p);
+        if (*d) batch_free(b, *d);
+        *d = p;
+        *cap = (int)nc;
+    }
+    if (count && hipMemcpy(*d, src, count * each, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(nullptr, LBM_EDEVICE, "batch upload failed");
+    return LBM_OK;
+}
+
+// Tile list of a batch group for `wpb` rows per workgroup: the members' tiles
+// (instance = position in the group) in the XCD-run order.  Instances stay
+// contiguous, so each XCD works on few grids.
+static std::vector<int4> group_tile_list(const lbm_batch *b, const std::vector<int> &members, int wpb)
 {
     std::vector<int4> nat;
     int inst = 0;
@@ -1309,58 +1382,48 @@ static int group_tiles(lbm_batch *b, const std::vector<int> &members, int wpb, i
         auto t = make_tiles(inst++, g->n1, g->n2, wpb, g->q);
         nat.insert(nat.end(), t.begin(), t.end());
     }
-    // largest instances' tiles first would help tail balance; keep the
-    // natural order (instances contiguous) so each XCD works on few grids
-    auto ord = xcd_order(nat, 1 << 30);
+    return xcd_order(nat, 1 << 30);
+}
+
+// the same, uploaded to a new device allocation the batch owns
+static int group_tiles(lbm_batch *b, const std::vector<int> &members, int wpb, int4 **d_out, int *nt_out, int *cap_out)
+{
+    const auto ord = group_tile_list(b, members, wpb);
     void *dt = nullptr;
-    if (hipMalloc(&dt, ord.size() * sizeof(int4)) != hipSuccess) return fail(nullptr, LBM_ENOMEM, "batch allocation failed");
-    b->allocs.push_back(dt);
-    if (hipMemcpy(dt, ord.data(), ord.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
-        return fail(nullptr, LBM_EDEVICE, "batch upload failed");
+    int cap = 0;
+    const int rc = upload_grow(b, &dt, &cap, ord.data(), ord.size(), sizeof(int4));
+    if (rc != LBM_OK) return rc;
     *d_out = (int4 *)dt;
     *nt_out = (int)ord.size();
+    *cap_out = cap;
     return LBM_OK;
 }
 
-static void batch_free(lbm_batch *b, void *p)
+static bool same_kernel(const lbm_batch::Group &a, const lbm_batch::Group &c)
 {
-    auto it = std::find(b->allocs.begin(), b->allocs.end(), p);
-    if (it != b->allocs.end()) b->allocs.erase(it);
-    (void)hipFree(p);
+    return a.q == c.q && a.precision == c.precision && a.cell == c.cell && a.iter == c.iter && a.wide == c.wide;
 }
 
-int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
+// Group the batch's grids by step kernel (lattice, or 0 for a fused group
+// holding both; storage precision; table kind; fixed-point force passes; wide
+// addressing) and upload each group's instance descriptors and tile table.
+// A group whose kernel was there before keeps its device arrays (rewritten in
+// place, grown when too small) and its tuned launch shape.
+static int batch_regroup(lbm_batch *b)
 {
-    return lbm_batch_create_ex(grids, n, 0u, out);
-}
-
-int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_batch **out)
-{
-    if (!grids || n <= 0 || !out || (flags & ~(uint32_t)LBM_BATCH_FUSE_LATTICES))
-        return fail(nullptr, LBM_EINVAL, "bad batch arguments");
-    const bool fuse = (flags & LBM_BATCH_FUSE_LATTICES) != 0;
-    *out = nullptr;
-    lbm_batch *b = new lbm_batch();
-    b->stream = grids[0]->stream;
-    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
-    for (int k = 0; k < n; ++k) {
-        lbm_grid *g = grids[k];
-        if (!g || !g->inited) {
-            delete b;
-            return fail(nullptr, LBM_ESTATE, "every grid of a batch must be initialised");
-        }
-        if (std::find(b->grids.begin(), b->grids.end(), g) != b->grids.end()) {
-            delete b;
-            return fail(nullptr, LBM_EINVAL, "a grid appears twice in the batch");
-        }
-        if (g->stream != b->stream && std::find(b->others.begin(), b->others.end(), g->stream) == b->others.end())
-            b->others.push_back(g->stream);
-        b->grids.push_back(g);
+    const bool fuse = (b->flags & LBM_BATCH_FUSE_LATTICES) != 0;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> keyed;
+    for (int k = 0; k < (int)b->grids.size(); ++k) {
+        const lbm_grid *g = b->grids[k];
         // wide grids keep their lattice's kernel (the fused one addresses whole buffers)
-        groups[std::make_tuple(fuse && !g->wide ? 0 : g->q, g->precision, g->ct, g->h_inst.iters > 0 ? 1 : 0, g->wide)]
+        keyed[std::make_tuple(fuse && !g->wide ? 0 : g->q, g->precision, g->ct, g->h_inst.iters > 0 ? 1 : 0, g->wide)]
             .push_back(k);
     }
-    for (auto &kv : groups) {
+    std::vector<lbm_batch::Group> old;
+    old.swap(b->groups);
+    std::vector<bool> kept(old.size(), false);
+    int rc = LBM_OK;
+    for (auto &kv : keyed) {
         lbm_batch::Group G;
         // a fused group with a single lattice keeps that lattice's kernel
         G.q = b->grids[kv.second[0]]->q;
@@ -1372,39 +1435,201 @@ int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_b
         G.wide = std::get<4>(kv.first);
         G.wpb = b->grids[kv.second[0]]->wpb;
         G.cap = b->grids[kv.second[0]]->cap;
+        for (size_t o = 0; o < old.size(); ++o)
+            if (!kept[o] && same_kernel(old[o], G)) {
+                kept[o] = true;
+                G.d_inst = old[o].d_inst;
+                G.inst_cap = old[o].inst_cap;
+                G.d_tiles = old[o].d_tiles;
+                G.tile_cap = old[o].tile_cap;
+                G.wpb = old[o].wpb;
+                G.cap = old[o].cap;
+                break;
+            }
         G.members = kv.second;
         std::vector<InstDesc> descs;
-        for (int k : kv.second) {
-            lbm_grid *g = b->grids[k];
+        for (int k : G.members) {
+            const lbm_grid *g = b->grids[k];
             InstDesc I = g->h_inst;
-            I.par0 = g->par;
+            // step s of the batch runs with par = s & 1; the grid's current buffer is g->par
+            I.par0 = g->par ^ (int)(b->step & 1);
             descs.push_back(I);
         }
-        void *di = nullptr;
-        if (hipMalloc(&di, descs.size() * sizeof(InstDesc)) != hipSuccess) {
-            lbm_batch_destroy(b);
-            return fail(nullptr, LBM_ENOMEM, "batch allocation failed");
-        }
-        b->allocs.push_back(di);
-        if (hipMemcpy(di, descs.data(), descs.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess) {
-            lbm_batch_destroy(b);
-            return fail(nullptr, LBM_EDEVICE, "batch upload failed");
-        }
-        G.d_inst = (InstDesc *)di;
-        const int rc = group_tiles(b, G.members, G.wpb, &G.d_tiles, &G.ntiles);
-        if (rc != LBM_OK) {
-            lbm_batch_destroy(b);
-            return rc;
-        }
+        const auto tiles = group_tile_list(b, G.members, G.wpb);
+        G.ntiles = (int)tiles.size();
         b->groups.push_back(G);
+        lbm_batch::Group &H = b->groups.back();
+        if ((rc = upload_grow(b, (void **)&H.d_inst, &H.inst_cap, descs.data(), descs.size(), sizeof(InstDesc))) != LBM_OK ||
+            (rc = upload_grow(b, (void **)&H.d_tiles, &H.tile_cap, tiles.data(), tiles.size(), sizeof(int4))) != LBM_OK)
+            break;
     }
+    for (size_t o = 0; o < old.size(); ++o)
+        if (!kept[o]) {
+            if (old[o].d_inst) batch_free(b, old[o].d_inst);
+            if (old[o].d_tiles) batch_free(b, old[o].d_tiles);
+        }
+    return rc;
+}
+
+// kernel node of group gi at batch parity par
+static void batch_node_params(const lbm_batch *b, int gi, hipKernelNodeParams &p, void **args)
+{
+    const auto &G = b->groups[gi];
+    p = hipKernelNodeParams{};
+    p.func = (void *)pick_step(G.q, G.precision, G.cell, 0, G.iter, G.wide);
+    p.gridDim = dim3(G.ntiles);
+    p.blockDim = dim3(64 * G.wpb);
+    p.sharedMemBytes = step_lds(G.cell, G.q, G.precision, G.cap, G.wpb);
+    p.kernelParams = args;
+    p.extra = nullptr;
+}
+
+static const int BATCH_GS = 16;   // steps per graph launch
+
+// The step graph: BATCH_GS steps, each one kernel node per group, chained.
+static int batch_build_graph(lbm_batch *b)
+{
+    batch_drop_graph(b);
+    if (hipGraphCreate(&b->gtmpl, 0) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "graph creation failed");
+    hipGraphNode_t prev = nullptr;
+    for (int s = 0; s < BATCH_GS; ++s)
+        for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
+            const InstDesc *a0 = b->groups[gi].d_inst;
+            const int4 *a1 = b->groups[gi].d_tiles;
+            int a2 = s & 1;
+            void *args[3] = {(void *)&a0, (void *)&a1, (void *)&a2};
+            hipKernelNodeParams p;
+            batch_node_params(b, gi, p, args);
+            hipGraphNode_t node = nullptr;
+            if (hipGraphAddKernelNode(&node, b->gtmpl, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess) {
+                batch_drop_graph(b);
+                return fail(nullptr, LBM_EDEVICE, "graph node creation failed");
+            }
+            b->nodes.push_back({node, gi, s & 1});
+            prev = node;
+        }
+    if (hipGraphInstantiate(&b->gexec, b->gtmpl, nullptr, nullptr, 0) != hipSuccess) {
+        batch_drop_graph(b);
+        return fail(nullptr, LBM_EDEVICE, "graph instantiation failed");
+    }
+    return LBM_OK;
+}
+
+// After a membership change that kept every group's kernel: the nodes of the
+// instantiated graph take the new grid sizes and tables in place.  Any
+// failure drops the graph (the next step builds a new one).
+static void batch_update_graph(lbm_batch *b)
+{
+    for (const auto &nd : b->nodes) {
+        const InstDesc *a0 = b->groups[nd.group].d_inst;
+        const int4 *a1 = b->groups[nd.group].d_tiles;
+        int a2 = nd.par;
+        void *args[3] = {(void *)&a0, (void *)&a1, (void *)&a2};
+        hipKernelNodeParams p;
+        batch_node_params(b, nd.group, p, args);
+        if (hipGraphExecKernelNodeSetParams(b->gexec, nd.node, &p) != hipSuccess) {
+            (void)hipGetLastError();
+            batch_drop_graph(b);
+            return;
+        }
+    }
+}
+
+// Make `grids` the batch's members.  The batch keeps its stream unless that
+// stream is owned by a grid that leaves (then it moves, in stream order, to
+// the first remaining grid's stream, or to a stream of its own).
+static int batch_set_members(lbm_batch *b, lbm_grid *const *grids, int32_t n)
+{
+    std::vector<lbm_grid *> list;
+    for (int k = 0; k < n; ++k) {
+        lbm_grid *g = grids[k];
+        if (!g || !g->inited) return fail(nullptr, LBM_ESTATE, "every grid of a batch must be initialised");
+        if (std::find(list.begin(), list.end(), g) != list.end()) return fail(nullptr, LBM_EINVAL, "a grid appears twice in the batch");
+        list.push_back(g);
+    }
+    bool stream_leaves = false;
+    for (lbm_grid *g : b->grids)
+        if (g && std::find(list.begin(), list.end(), g) == list.end()) {
+            g->batches.erase(std::remove(g->batches.begin(), g->batches.end(), b), g->batches.end());
+            if (g->own_stream && g->stream == b->stream) stream_leaves = true;
+        }
+    if (stream_leaves) {
+        hipStream_t ns = nullptr;
+        if (!list.empty()) {
+            ns = list[0]->stream;
+        } else if (hipStreamCreate(&ns) != hipSuccess) {
+            b->broken = true;
+            return fail(nullptr, LBM_EDEVICE, "hipStreamCreate failed");
+        }
+        if (hipEventRecord(b->ev, b->stream) != hipSuccess || hipStreamWaitEvent(ns, b->ev, 0) != hipSuccess) {
+            b->broken = true;
+            return fail(nullptr, LBM_EDEVICE, "stream handover failed");
+        }
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
+        b->own_stream = list.empty();
+        b->stream = ns;
+    }
+    for (lbm_grid *g : list)
+        if (std::find(g->batches.begin(), g->batches.end(), b) == g->batches.end()) g->batches.push_back(b);
+    b->grids = list;
+    b->others.clear();
+    for (lbm_grid *g : list)
+        if (g->stream != b->stream && std::find(b->others.begin(), b->others.end(), g->stream) == b->others.end())
+            b->others.push_back(g->stream);
+    std::vector<lbm_batch::Group> before = b->groups;
+    const int rc = batch_regroup(b);
+    if (rc != LBM_OK) {
+        b->broken = true;
+        batch_drop_graph(b);
+        return rc;
+    }
+    bool same = before.size() == b->groups.size();
+    for (size_t k = 0; same && k < before.size(); ++k) same = same_kernel(before[k], b->groups[k]);
+    if (b->gexec) {
+        if (same) batch_update_graph(b);
+        else batch_drop_graph(b);
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_create(lbm_grid *const *grids, int32_t n, lbm_batch **out)
+{
+    return lbm_batch_create_ex(grids, n, 0u, out);
+}
+
+int lbm_batch_create_ex(lbm_grid *const *grids, int32_t n, uint32_t flags, lbm_batch **out)
+{
+    if (!grids || n <= 0 || !out || (flags & ~(uint32_t)LBM_BATCH_FUSE_LATTICES))
+        return fail(nullptr, LBM_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    if (!grids[0]) return fail(nullptr, LBM_ESTATE, "every grid of a batch must be initialised");
+    lbm_batch *b = new lbm_batch();
+    b->stream = grids[0]->stream;
+    b->flags = flags;
     if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) {
-        lbm_batch_destroy(b);
+        delete b;
         return fail(nullptr, LBM_EDEVICE, "event creation failed");
     }
-    for (lbm_grid *g : b->grids) g->batches.push_back(b);
+    const int rc = batch_set_members(b, grids, n);
+    if (rc != LBM_OK) {
+        const std::string msg = g_last_error;
+        lbm_batch_destroy(b);
+        g_last_error = msg;
+        return rc;
+    }
     *out = b;
     return LBM_OK;
+}
+
+int lbm_batch_update(lbm_batch *b, lbm_grid *const *grids, int32_t n)
+{
+    if (!b || n < 0 || (n > 0 && !grids)) return fail(nullptr, LBM_EINVAL, "bad batch update arguments");
+    if (const int u = batch_usable(b)) return u;
+    // the tables are rewritten: the steps already queued must be done with them
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "sync failed");
+    for (hipStream_t s : b->others)
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "sync failed");
+    return batch_set_members(b, grids, n);
 }
 
 // grids on other streams: the batch stream waits for their pending work before
@@ -1442,7 +1667,11 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
 {
     if (!b || n < 0) return fail(nullptr, LBM_EINVAL, "bad batch step arguments");
     if (const int u = batch_usable(b)) return u;
-    const int GS = 16;
+    if (b->groups.empty()) {            // no members: time passes, nothing to step
+        b->step += n;
+        return LBM_OK;
+    }
+    const int GS = BATCH_GS;
     int64_t left = n;
     {
         const int rc = batch_join_in(b);
@@ -1450,19 +1679,12 @@ int lbm_batch_step(lbm_batch *b, int64_t n)
     }
     // the batch's own parity: step s of the batch uses par = s & 1
     if (left >= GS && (b->step & 1) == 0) {
-        if (!b->graph.exec) {
-            hipGraph_t graph = nullptr;
-            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                return fail(nullptr, LBM_EDEVICE, "capture failed");
-            for (int s = 0; s < GS; ++s) batch_launch(b, s & 1);
-            if (hipStreamEndCapture(b->stream, &graph) != hipSuccess ||
-                hipGraphInstantiate(&b->graph.exec, graph, nullptr, nullptr, 0) != hipSuccess)
-                return fail(nullptr, LBM_EDEVICE, "graph instantiation failed");
-            (void)hipGraphDestroy(graph);
-            b->graph.steps = GS;
+        if (!b->gexec) {
+            const int rc = batch_build_graph(b);
+            if (rc != LBM_OK) return rc;
         }
         while (left >= GS) {
-            if (hipGraphLaunch(b->graph.exec, b->stream) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "graph launch failed");
+            if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "graph launch failed");
             left -= GS;
             b->step += GS;
         }
@@ -1484,9 +1706,15 @@ int lbm_batch_residuals(lbm_batch *b, lbm_resid *out)
     if (!b || !out) return fail(nullptr, LBM_EINVAL, "null argument");
     if (const int u = batch_usable(b)) return u;
     const size_t n = b->grids.size();
-    if (!b->d_res) {
-        if (hipMalloc((void **)&b->d_res, n * RED_NF * 8) != hipSuccess) return fail(nullptr, LBM_ENOMEM, "allocation failed");
-        b->allocs.push_back(b->d_res);
+    if (n == 0) return LBM_OK;
+    if (!b->d_res || n > b->res_cap) {
+        double *p = nullptr;
+        const size_t cap = std::max(n, 2 * b->res_cap);
+        if (hipMalloc((void **)&p, cap * RED_NF * 8) != hipSuccess) return fail(nullptr, LBM_ENOMEM, "allocation failed");
+        b->allocs.push_back(p);
+        if (b->d_res) batch_free(b, b->d_res);
+        b->d_res = p;
+        b->res_cap = cap;
     }
     for (size_t k = 0; k < n; ++k) {
         const int rc = launch_reduce(b->grids[k], 1, b->d_res + k * RED_NF);
@@ -1509,7 +1737,10 @@ int lbm_batch_residuals(lbm_batch *b, lbm_resid *out)
 int lbm_batch_info(const lbm_batch *b, int32_t group, int32_t *q, int32_t *precision, int64_t *cells)
 {
     if (!b) return fail(nullptr, LBM_EINVAL, "null batch");
-    if (group < 0 || group >= (int32_t)b->groups.size()) return fail(nullptr, LBM_EINVAL, "no such group");
+    if (group < 0 || group >= (int32_t)b->groups.size()) {
+        if (q || precision || cells) return fail(nullptr, LBM_EINVAL, "no such group");
+        return (int)b->groups.size();   // the count alone (also for an empty batch)
+    }
     const auto &G = b->groups[group];
     if (q) *q = G.q;
     if (precision) *precision = G.precision;
@@ -1557,12 +1788,13 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps)
     int64_t advanced = 0;
     for (auto &G : b->groups) {
         int4 *tiles[3] = {nullptr, nullptr, nullptr};
-        int nts[3] = {0, 0, 0};
+        int nts[3] = {0, 0, 0}, tcaps[3] = {0, 0, 0};
         for (int s = 0; s < 3; ++s) {
             if (shapes[s] == G.wpb) {
                 tiles[s] = G.d_tiles;
                 nts[s] = G.ntiles;
-            } else if ((rc = group_tiles(b, G.members, shapes[s], &tiles[s], &nts[s])) != LBM_OK) {
+                tcaps[s] = G.tile_cap;
+            } else if ((rc = group_tiles(b, G.members, shapes[s], &tiles[s], &nts[s], &tcaps[s])) != LBM_OK) {
                 return rc;
             }
         }
@@ -1597,13 +1829,12 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps)
         G.cap = best_c;
         G.d_tiles = tiles[best_s];
         G.ntiles = nts[best_s];
+        G.tile_cap = tcaps[best_s];
     }
     // every grid advanced by the same even number of steps, as lbm_batch_step would have moved it
     b->step += advanced;
     for (lbm_grid *g : b->grids) g->step += advanced;
-    if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
-    b->graph.exec = nullptr;
-    b->graph.steps = 0;
+    batch_drop_graph(b);
     return batch_join_out(b);
 }
 

@@ -5,9 +5,11 @@ computes any step of the method.  Loading fails loudly when the library has
 not been built (``python -m paper_2301_01868_amd.build``).
 
 PyTorch ships its own HIP runtime with the same soname (libamdhip64.so.7) as
-the ROCm one the library links; a process uses the first one loaded for both
-only if torch is imported first.  Import torch before the first ``load()``
-when passing torch streams or torch memory to the library.
+the ROCm one the library links.  Whichever is loaded first serves both, but
+torch's device initialisation fails on the ROCm one ("no ROCm-capable
+device"), so ``load()`` imports torch (when it is installed) before it opens
+the library: torch streams and torch memory then work with the library in
+any order of use.
 """
 from __future__ import annotations
 
@@ -32,7 +34,8 @@ EXPORTED = ["lbm_lattice", "lbm_grid_create", "lbm_grid_destroy", "lbm_last_erro
             "lbm_get_state", "lbm_set_state", "lbm_save", "lbm_load", "lbm_physical_velocity", "lbm_stream_map", "lbm_geometry", "lbm_synchronize",
             "lbm_stream", "lbm_batch_create", "lbm_batch_create_ex", "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_residuals", "lbm_batch_info", "lbm_batch_step_group", "lbm_set_launch", "lbm_set_occupancy", "lbm_autotune",
             "lbm_copy_probe", "lbm_bandwidth_probe", "lbm_map_planar", "lbm_map_polar",
-            "lbm_batch_autotune", "lbm_batch_group_launch", "lbm_get_state_noalloc"]
+            "lbm_batch_autotune", "lbm_batch_group_launch", "lbm_get_state_noalloc", "lbm_grid_set_stream",
+            "lbm_batch_update"]
 
 
 class LbmError(RuntimeError):
@@ -81,6 +84,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("HIP library not built: %s (run python -m paper_2301_01868_amd.build)" % LIB_PATH)
+    try:
+        import torch  # noqa: F401  (its HIP runtime first: see the module notes)
+    except ImportError:
+        pass
     L = ct.CDLL(LIB_PATH)
     D = ct.POINTER(ct.c_double)
     I32 = ct.POINTER(ct.c_int32)
@@ -110,6 +117,8 @@ def load():
     L.lbm_synchronize.argtypes = [vp]
     L.lbm_stream.argtypes = [vp]
     L.lbm_stream.restype = vp
+    L.lbm_grid_set_stream.argtypes = [vp, vp]
+    L.lbm_batch_update.argtypes = [vp, ct.POINTER(vp), ct.c_int32]
     L.lbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int32, ct.POINTER(vp)]
     L.lbm_batch_create_ex.argtypes = [ct.POINTER(vp), ct.c_int32, ct.c_uint32, ct.POINTER(vp)]
     L.lbm_batch_step.argtypes = [vp, ct.c_int64]
@@ -299,6 +308,12 @@ def lbm_stream(h):
     return load().lbm_stream(h)
 
 
+def lbm_grid_set_stream(h, stream):
+    """Move the grid's later work to `stream` (a raw hipStream_t value, or
+    None for a library-owned stream); queued work stays ordered before it."""
+    _chk(load().lbm_grid_set_stream(h, stream), h)
+
+
 def lbm_autotune(h, steps=20):
     rc = load().lbm_autotune(h, int(steps))
     if rc < 0:
@@ -346,6 +361,13 @@ def lbm_batch_create_ex(handles, flags=0):
     b = ct.c_void_p()
     _chk(load().lbm_batch_create_ex(arr, len(handles), ct.c_uint32(flags), ct.byref(b)))
     return b
+
+
+def lbm_batch_update(b, handles):
+    """Make `handles` the batch's members in place (continuous batching)."""
+    hs = [h.value if isinstance(h, ct.c_void_p) else h for h in handles]
+    arr = (ct.c_void_p * max(1, len(hs)))(*hs)
+    _chk(load().lbm_batch_update(b, arr, len(hs)))
 
 
 def lbm_batch_step(b, n):
@@ -495,3 +517,6 @@ class Grid:
     @property
     def stream(self):
         return lbm_stream(self.h)
+
+    def set_stream(self, stream):
+        lbm_grid_set_stream(self.h, stream)

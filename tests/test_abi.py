@@ -100,6 +100,8 @@ def test_null_arguments_are_rejected(lib):
     assert lib.lbm_grid_create(None, ct.byref(h)) == lbm.LBM_EINVAL
     assert lib.lbm_batch_create(None, 1, ct.byref(h)) == lbm.LBM_EINVAL
     assert lib.lbm_batch_create_ex(None, 1, 0, ct.byref(h)) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_update(None, None, 0) == lbm.LBM_EINVAL
+    assert lib.lbm_grid_set_stream(None, None) == lbm.LBM_EINVAL
     assert lib.lbm_init(None, None) == lbm.LBM_EINVAL
     assert lib.lbm_step(None, ct.c_int64(1)) == lbm.LBM_EINVAL
     assert lib.lbm_set_occupancy(None, 0) == lbm.LBM_EINVAL

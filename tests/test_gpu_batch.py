@@ -194,10 +194,19 @@ def test_batch_rejects_repeated_or_uninitialised_grids():
     b.init()
     bt = lbm.lbm_batch_create([a.h, b.h])
     lbm.lbm_batch_step(bt, 4)
+    # an update naming a grid twice or an uninitialised one leaves the batch as it was
+    c = lbm.Grid(case, precision=lbm.LBM_FP32)
+    for bad, code in (([a.h, a.h], lbm.LBM_EINVAL), ([a.h, c.h], lbm.LBM_ESTATE)):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_batch_update(bt, bad)
+        assert e.value.code == code
+    lbm.lbm_batch_step(bt, 4)
+    assert [g[2] for g in lbm.lbm_batch_groups(bt)] == [2 * case.ncell]
     lbm.lbm_batch_destroy(bt)
     Pa, _ = a.get_state()
     Pb, _ = b.get_state()
     assert np.array_equal(Pa, Pb)
+    assert a.info.step == 8
 
 
 def test_batch_with_fixed_point_force_grids():
@@ -276,3 +285,87 @@ def test_grid_destroyed_before_its_batch():
     grids[1].step(10)
     assert grids[1].residual().bad_cells == 0
     assert grids[1].info.step == 30
+
+
+@pytest.mark.parametrize("fuse", [0, lbm.LBM_BATCH_FUSE_LATTICES], ids=["per_lattice", "fused"])
+def test_batch_update_in_place_equals_alone(fuse):
+    """Continuous batching: members leave and join a running batch (at an odd
+    batch step, with grids of either buffer parity, and through a change of
+    group structure) and every grid ends bitwise as the same steps taken
+    alone.  Steps of 48 run as graph replays whose kernel nodes the updates
+    rewrite in place; odd counts add single launches."""
+    cases = _cases()
+    alone = [lbm.Grid(c, precision=lbm.LBM_FP32) for c in cases]
+    mixed = [lbm.Grid(c, precision=lbm.LBM_FP32) for c in cases]
+    for g in alone + mixed:
+        g.init()
+    # grid 3 joins with the other buffer parity
+    for g in (alone[3], mixed[3]):
+        g.step(5)
+    plan = [([0, 1], 48), ([0, 1, 2], 33), ([1, 2, 3], 48), ([1, 2, 3, 4], 64), ([4], 16), ([], 10),
+            ([0, 2, 4], 48)]
+    b = lbm.lbm_batch_create_ex([mixed[k].h for k in plan[0][0]], fuse)
+    for members, n in plan:
+        lbm.lbm_batch_update(b, [mixed[k].h for k in members])
+        say("members", members, "groups", lbm.lbm_batch_groups(b))
+        lbm.lbm_batch_step(b, n)
+        for k in members:
+            alone[k].step(n)
+    # grids outside the batch step alone too
+    mixed[3].step(7)
+    alone[3].step(7)
+    lbm.lbm_batch_destroy(b)
+    for ga, gm, c in zip(alone, mixed, cases):
+        assert ga.info.step == gm.info.step
+        Pa, sa = ga.get_state()
+        Pm, sm = gm.get_state()
+        assert np.array_equal(Pa, Pm), c.meta
+        assert np.array_equal(sa, sm)
+
+
+def test_batch_update_moves_off_a_leaving_grids_stream():
+    """The batch runs on its first grid's library-owned stream; when that grid
+    leaves and is destroyed, the batch has moved to a remaining grid's stream
+    and keeps stepping correctly."""
+    cases = [G.circular_couette(21, 12, 100, 10.0, u_inner=0.05, tau=0.8),
+             G.planar_couette(9, G.faces_uniform(8), n2=70, u_wall=0.05, tau=0.8)]
+    grids = [lbm.Grid(c, precision=lbm.LBM_FP32) for c in cases]
+    ref = lbm.Grid(cases[1], precision=lbm.LBM_FP32)
+    for g in grids + [ref]:
+        g.init()
+    b = lbm.lbm_batch_create([g.h for g in grids])
+    lbm.lbm_batch_step(b, 20)
+    lbm.lbm_batch_update(b, [grids[1].h])
+    grids[0].close()
+    lbm.lbm_batch_step(b, 20)
+    lbm.lbm_batch_residuals(b, 1)
+    lbm.lbm_batch_destroy(b)
+    ref.step(40)
+    assert np.array_equal(ref.get_state()[0], grids[1].get_state()[0])
+
+
+def test_grid_created_on_a_setup_stream_then_moved():
+    """A grid created and initialised on one stream and handed to another
+    (lbm_grid_set_stream) steps exactly like one made on the second stream."""
+    import torch
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    c = _cases()[0]
+    a = lbm.Grid(c, precision=lbm.LBM_FP32, stream=s2.cuda_stream)
+    g = lbm.Grid(c, precision=lbm.LBM_FP32, stream=s1.cuda_stream)
+    a.init()
+    g.init()
+    g.set_stream(s2.cuda_stream)
+    assert g.stream == s2.cuda_stream
+    a.step(50)
+    g.step(50)
+    assert np.array_equal(a.get_state()[0], g.get_state()[0])
+    # a grid held by a batch keeps its stream
+    b = lbm.lbm_batch_create([g.h])
+    with pytest.raises(lbm.LbmError) as e:
+        g.set_stream(s1.cuda_stream)
+    assert e.value.code == lbm.LBM_ESTATE
+    lbm.lbm_batch_destroy(b)
+    g.set_stream(None)          # to a library-owned stream
+    g.step(2)
+    a.step(2)
+    assert np.array_equal(a.get_state()[0], g.get_state()[0])
