@@ -82,6 +82,9 @@ def workloads():
         # q2, so the step rebuilds them per cell from the staged geometry
         "wobbled_box_q21_1024x1024": lambda: [G.periodic_box(21, 1024, 1024, dx=1.0, dy=1.1, skew=0.1, wobble=0.25,
                                                              tau=0.9)],
+        # the wobbled box at HBM scale (8.4 M cells, 0.7 GB per FP32 population buffer)
+        "wobbled_box_q21_2048x4096": lambda: [G.periodic_box(21, 2048, 4096, dx=1.0, dy=1.1, skew=0.1, wobble=0.25,
+                                                             tau=0.9)],
         # the same box without the wobble: constant metric terms, so per-row tables (or, with
         # --geometry cell / cell_table, the per-cell paths on identical geometry)
         "sheared_box_q21_1024x1024": lambda: [G.periodic_box(21, 1024, 1024, dx=1.0, dy=1.1, skew=0.1, wobble=0.0,
@@ -435,6 +438,9 @@ def serve_bench(args):
     import torch
     from paper_2301_01868_amd import serve, lbm
 
+    def note(text):
+        print(text, file=sys.stderr, flush=True)
+
     stream, setup = torch.cuda.Stream(), torch.cuda.Stream()
     budget = 8 << 30
     tol = 1e-8
@@ -442,14 +448,17 @@ def serve_bench(args):
     # 1. batched capacity on this request mix
     cal = serve.make_trace(seed=2301_01870, rate=1e9, n_requests=args.cal_requests, tol=tol)
     srv = serve.Server(hbm_budget=budget, check_every=256, stream=stream, setup_stream=setup)
-    st = srv.run(cal, realtime=False, stop_after=args.cal_seconds)
+    note("capacity run: %d requests for %.0f s" % (len(cal), args.cal_seconds))
+    st = srv.run(cal, realtime=False, stop_after=args.cal_seconds, progress=note)
     capacity = st["lattice_updates"] / st["makespan"]
+    note("capacity %.3g lattice updates/s" % capacity)
     # 2. the served trace
     rate = args.rate if args.rate > 0 else args.load * capacity / mean_lu
     trace = serve.make_trace(seed=2301_01869, rate=rate, n_requests=args.requests, tol=tol)
     base = copy.deepcopy(trace)
     srv = serve.Server(hbm_budget=budget, check_every=256, stream=stream, setup_stream=setup)
-    info = srv.run(trace, realtime=True)
+    note("served trace: %d requests at %.4g per s" % (len(trace), rate))
+    info = srv.run(trace, realtime=True, progress=note)
     s_b = serve.summarize(trace, info["makespan"])
     s_b.update({k: info[k] for k in ("rounds", "setup_s", "check_s", "retire_s", "peak_resident")})
     # 3. sequential FP64 on a seeded sample, back to back (service times only)
@@ -461,8 +470,9 @@ def serve_bench(args):
         sample = [base[i] for i in idx]
         for r in sample:
             r.arrival = 0.0
+        note("sequential FP64 replay of requests %s" % idx)
         info2 = serve.run_sequential(sample, precision=lbm.LBM_FP64, check_every=256, stream=ct_stream(stream),
-                                     realtime=False)
+                                     realtime=False, progress=note)
         lu_s = sum(r.steps * r.case.ncell for r in sample)
         ok = [r for r in sample if r.status == "converged"]
         seq = {"sample": idx, "requests": len(sample), "converged": len(ok),

@@ -272,11 +272,12 @@ class Server:
         r.admit_round = rounds
         return g
 
-    def run(self, requests, realtime=True, stop_after=None):
+    def run(self, requests, realtime=True, stop_after=None, progress=None):
         """Serve the trace.  With realtime=True arrivals are honoured against the
         wall clock; otherwise every request is available at time 0.
         stop_after (seconds) ends the run early, leaving unfinished requests
-        as they are (capacity measurements)."""
+        as they are (capacity measurements).  progress(text) is called about
+        every 20 s with the run's state."""
         pending = sorted(requests, key=lambda r: r.arrival)
         active = []          # [(request, Grid, bytes, max_steps, stall_steps)]
         used = 0
@@ -287,8 +288,14 @@ class Server:
         lu = 0
         t_setup = t_check = t_retire = 0.0
         peak = 0
+        finished = 0
+        t_note = t0
         try:
             while k < len(pending) or active:
+                if progress is not None and time.perf_counter() - t_note > 20.0:
+                    t_note = time.perf_counter()
+                    progress("t %.0f s: %d admitted, %d resident, %d finished, %.3g lattice updates"
+                             % (t_note - t0, k, len(active), finished, lu))
                 if stop_after is not None and time.perf_counter() - t0 > stop_after:
                     break
                 # 1. the round's steps run while the host admits
@@ -339,6 +346,7 @@ class Server:
                     tr = time.perf_counter()
                     now = tr - t0
                     for (r, g, need, _, _) in done:
+                        finished += 1
                         r.finish = now
                         m, U, Ut = g.moments()
                         r.result = {"Ut": Ut, "u": g.physical_velocity()}
@@ -360,9 +368,10 @@ class Server:
 
 
 def run_sequential(requests, precision=lbm.LBM_FP64, check_every=256, max_steps=2_000_000, stream=None,
-                   realtime=True, stall_steps=200_000):
+                   realtime=True, stall_steps=200_000, progress=None):
     """Plain one-solve-at-a-time stepping, first come first served: one grid,
-    check_every steps (graph launches), one residual check, repeat."""
+    check_every steps (graph launches), one residual check, repeat.
+    progress(text) is called after each request."""
     t0 = time.perf_counter()
     for r in sorted(requests, key=lambda r: r.arrival):
         now = time.perf_counter() - t0
@@ -383,6 +392,9 @@ def run_sequential(requests, precision=lbm.LBM_FP64, check_every=256, max_steps=
         r.result = {"Ut": Ut, "u": g.physical_velocity()}
         r.finish = time.perf_counter() - t0
         g.close()
+        if progress is not None:
+            progress("sequential: request %d (%s, N %d) %s after %d steps, %.1f s"
+                     % (r.rid, r.case.meta.get("problem"), r.case.n1, r.status, r.steps, r.finish - r.start))
     return {"makespan": time.perf_counter() - t0}
 
 
