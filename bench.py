@@ -166,7 +166,10 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
         else:
             grids[0].step(n)
 
-    run(warmup)
+    # a single grid captures its 32-step graph (per buffer parity) at its first
+    # call of 32 steps or more: warm that up too, with an even count so the
+    # timed steps start at the captured parity
+    run(warmup if batch is not None else max(warmup, 32) + (max(warmup, 32) & 1))
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -245,7 +248,8 @@ def measure3d(steps, warmup, stream):
     case = G3.circular_couette3(128, 512, 128.0, n3=64, dz=1.0, u_inner=0.05, tau=0.8)
     g = lbm3d.Grid3(case, stream=ct_stream(stream))
     g.init()
-    g.step(warmup)
+    # the step graph (32 steps per buffer parity) is captured in the warm-up
+    g.step(max(warmup, 32) + (max(warmup, 32) & 1))
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)

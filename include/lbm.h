@@ -69,8 +69,12 @@ enum {
 enum {
     LBM_GEOM_AUTO = 0,       /* per-row tables when the metric terms do not depend on q2,
                                 else as LBM_GEOM_CELL */
-    LBM_GEOM_CELL = 1,       /* per cell, rebuilt in the step from the FP64 geometry of the cell
-                                and its neighbours (staged in LDS; 32 or 64 B per cell) */
+    LBM_GEOM_CELL = 1,       /* per cell, rebuilt in the step from the geometry of the cell and
+                                its neighbours (staged in LDS: FP64 values for LBM_FP64, FP32
+                                deviations from a reference cell of the tile for offset storage;
+                                32 or 64 B per cell in HBM); offset storage with a base other
+                                than LBM_BASE_LOCAL_REST reads the stored table instead
+                                (table_kind 1) */
     LBM_GEOM_CELL_TABLE = 2  /* per cell, read from a stored table of every term (4Q + 3 values
                                 and more per cell) */
 };

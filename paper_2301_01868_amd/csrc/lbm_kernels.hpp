@@ -270,8 +270,17 @@ struct TabView {
 // The differences of neighbouring tangents are taken in FP64, so the
 // Christoffel sums keep the relative accuracy of the compute type where the
 // mapping varies slowly.  The base terms of offset storage come from the local
-// rest state, linear in (J, H) and evaluated in FP64:
+// rest state, linear in (J, H):
 //   J phi_rest,a = w_a [(2 - |c_a|^2 / (2 T0)) J + (c_a.H.c_a - T0 tr H) / (2 T0)]
+// FP64 compute (GeoTab) stages the FP64 geometry and takes the differences in
+// FP64.  FP32 compute (GeoTabF) stages FP32 deviations of every field from
+// its value at a reference cell of the tile's 4-row band (the band's first
+// row, the tile's first column; the same for every launch shape), rounded
+// once from FP64, and takes every difference and term in FP32: a difference
+// over one cell then carries the rounding of deviations of at most about 35
+// cells' variation, a few 1e-6 of itself, and the step needs no FP64
+// arithmetic per direction (which runs at half the FP32 rate and took most
+// of the kernel's vector ALU time).
 // ---------------------------------------------------------------------------
 enum { GE_G1X = 0, GE_G1Y, GE_G2X, GE_G2Y, GE_J, GE_H11, GE_H12, GE_H22, GE_NF };
 
@@ -295,29 +304,23 @@ __host__ __device__ constexpr int geo_tile_field()
 {
     return (4 + 2 * cmax<Q>()) * geo_tile_cols<Q>();
 }
-// LDS bytes of one workgroup's staged geometry
+// LDS bytes of one workgroup's staged geometry (FP64 values for FP64
+// compute, FP32 deviations for FP32 compute)
 template <int Q, typename T>
 __host__ __device__ constexpr unsigned geo_stage_bytes()
 {
-    return (unsigned)(geo_stage_fields<T>() * geo_tile_field<Q>() * sizeof(double));
+    return (unsigned)(geo_stage_fields<T>() * geo_tile_field<Q>() * sizeof(T));
 }
 
-// rho0-free local rest state J phi_rest of direction a; s = -1 reflects the
-// q1 component of c_a (specular source direction), which flips the c1 c2 term
-template <int Q>
-__device__ inline double jrest(int a, double J, double h11, double h12, double h22, double s = 1.0)
-{
-    constexpr double T0 = lattice_T0<Q>();
-    const double c1 = cx(a), c2 = cy(a);
-    const double cc = c1 * c1 + c2 * c2;
-    return weight<Q>(a) * ((2.0 - cc / (2.0 * T0)) * J +
-                           (c1 * c1 * h11 + 2.0 * s * c1 * c2 * h12 + c2 * c2 * h22 - T0 * (h11 + h22)) * (1.0 / (2.0 * T0)));
-}
-
-// Copy the geometry of the workgroup's rows tl.y .. tl.y + wpb - 1 and columns
-// tl.z .. tl.z + 63, with c_max layers around them, into the LDS tile.
-// Entries outside the stored range (rows or columns past the grid's
-// continuation) are zero and never read by a cell inside the grid.
+// Start copying the geometry of the workgroup's rows tl.y .. tl.y + wpb - 1
+// and columns tl.z .. tl.z + 63, with c_max layers around them, into the LDS
+// tile.  The loads go straight to LDS (no registers): each instruction moves
+// 64 consecutive dwords of a field's tile rows, which lie contiguously both
+// in LDS and, row by row, in the geometry array.  Rows and columns past the
+// stored range are clamped to it; those entries are never read by a cell
+// inside the grid.  The caller waits for the loads (s_waitcnt) and then for
+// the other waves (barrier) before reading the tile, and may issue other
+// loads in between.
 template <int Q, typename T>
 __device__ __forceinline__ const double *stage_geometry(const InstDesc *__restrict__ d, const int4 tl, int wave)
 {
@@ -328,54 +331,268 @@ __device__ __forceinline__ const double *stage_geometry(const InstDesc *__restri
     const int lane = (int)(threadIdx.x & 63);
     const int ger = d->n1 + 2 * CM, gw = d->gw;
     const double *__restrict__ ge = d->geo;
-    // each wave copies tile rows (one field, one row of 64 + 2 c_max cells),
-    // U rows per pass with all loads issued before the stores
+    const int nd = 2 * TR * TC;   // dwords of one field's tile rows
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const double *gf = ge + (size_t)f * d->gfs;
+        for (int k0 = wave * 64; k0 < nd; k0 += nw * 64) {
+            const int k = k0 + lane;
+            if (k < nd) {
+                const int e = k >> 1, rr = e / TC, cc = e - rr * TC;
+                const int er = min(tl.y + rr, ger - 1), ec = min(tl.z + cc, gw - 1);
+                const char *src = (const char *)(gf + (size_t)er * gw + ec) + (k & 1) * 4;
+                __builtin_amdgcn_global_load_lds(
+                    src, (__attribute__((address_space(3))) void *)((char *)(geo_lds + f * FS) + 4 * k0), 4, 0, 0);
+            }
+        }
+    }
+    return geo_lds;
+}
+
+// FP32 compute: stage, per field, the FP32 deviation of every tile entry
+// from the field's value at the reference cell (band row tl.y & ~3, column
+// tl.z), into the LDS tile; ref[f] receives those reference values.  All
+// loads of a pass are issued before its stores.  Returns the tile; the
+// caller waits for the other waves (barrier) before reading it.
+template <int Q>
+__device__ __forceinline__ const float *stage_geometry_f(const InstDesc *__restrict__ d, const int4 tl, int wave,
+                                                         double (&ref)[GE_NF])
+{
+    extern __shared__ float geo_ldsf[];
+    constexpr int CM = cmax<Q>(), TC = geo_tile_cols<Q>(), FS = geo_tile_field<Q>();
+    const int nw = (int)(blockDim.x >> 6), TR = nw + 2 * CM;
+    const int lane = (int)(threadIdx.x & 63);
+    const int ger = d->n1 + 2 * CM, gw = d->gw;
+    const double *__restrict__ ge = d->geo;
+    const size_t gfs = (size_t)d->gfs;
+    // reference cell (extended indices: cell row r is geometry row r + c_max)
+    const size_t rc = (size_t)((tl.y & ~3) + CM) * gw + (size_t)(tl.z + CM);
+#pragma unroll
+    for (int f = 0; f < GE_NF; ++f) ref[f] = ge[f * gfs + rc];
+    // each wave takes whole tile rows (one field, one row of 64 + 2 c_max
+    // entries: lanes 0-63 and, for the last 2 c_max, lanes 0 .. 2 c_max - 1
+    // again), U rows per pass with every load issued before the stores
     constexpr int U = 4;
-    for (int row0 = wave; row0 < NF * TR; row0 += U * nw) {
+    const int nrows = GE_NF * TR;
+    for (int t0 = wave; t0 < nrows; t0 += U * nw) {
         double v[U][2];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int row = row0 + u * nw;
-            const int f = row / TR, rr = row - f * TR;
-            const int er = tl.y + rr;
-            const double *src = ge + (size_t)f * d->gfs + (size_t)er * gw + tl.z;
+            const int t = t0 + u * nw;
+            const int f = t / TR, rr = t - f * TR;
+            const int er = min(tl.y + rr, ger - 1);
+            const double *src = ge + f * gfs + (size_t)er * gw;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int cc = lane + 64 * h;
-                v[u][h] = (row < NF * TR && cc < TC && er < ger && tl.z + cc < gw) ? src[cc] : 0.0;
+                v[u][h] = (t < nrows && cc < TC) ? src[min(tl.z + cc, gw - 1)] : 0.0;
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int row = row0 + u * nw;
+            const int t = t0 + u * nw;
+            if (t < nrows) {
+                const int f = t / TR, rr = t - f * TR;
+                double r = ref[0];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int cc = lane + 64 * h;
-                if (row < NF * TR && cc < TC) {
-                    const int f = row / TR, rr = row - f * TR;
-                    geo_lds[f * FS + rr * TC + cc] = v[u][h];
+                for (int g = 1; g < GE_NF; ++g)
+                    if (f == g) r = ref[g];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int cc = lane + 64 * h;
+                    if (cc < TC) geo_ldsf[f * FS + rr * TC + cc] = (float)(v[u][h] - r);
                 }
             }
         }
     }
-    __syncthreads();
-    return geo_lds;
+    return geo_ldsf;
 }
 
-template <int Q, typename T>
-struct GeoTab {
+// Rebuilt table fields for FP32 compute, from the staged FP32 deviations.
+template <int Q>
+struct GeoTabF {
+    using T = float;
     using TB = Tab<Q>;
     static constexpr int CM = cmax<Q>();
     static constexpr double T0 = lattice_T0<Q>();
-    // offsets: compute relative to the local rest state (FP32 compute), else
-    // with the particle numbers themselves (FP64)
-    static constexpr bool CB = sizeof(T) == 4;
+    static constexpr int TC = geo_tile_cols<Q>(), FS = geo_tile_field<Q>();
+    const float *L;    // staged deviations
+    int o;             // own cell in a staged field
+    int i, n1, per1, bclo, bchi;
+    float eJ, e11, e12, e22, e1x, e1y, e2x, e2y;   // own deviations
+    float rho0f, r12;  // rho0, reference H12 (for mirrored sources)
+    T u1x, u1y, u2x, u2y, G11, G12, G22, mb, c1s, c2s, kpi;
+
+    __device__ __forceinline__ float ld(int f, int dr, int dc) const { return L[o + (f * FS + dr * TC + dc)]; }
+
+    // e_a(q + c_a) - e_a(q)
+    __device__ __forceinline__ void dA(int a, T &dx, T &dy) const
+    {
+        const int c1 = cx(a), c2 = cy(a);
+        dx = 0.f;
+        dy = 0.f;
+        if (c1 != 0) {
+            dx += (T)c1 * (ld(GE_G1X, c1, c2) - e1x);
+            dy += (T)c1 * (ld(GE_G1Y, c1, c2) - e1y);
+        }
+        if (c2 != 0) {
+            dx += (T)c2 * (ld(GE_G2X, c1, c2) - e2x);
+            dy += (T)c2 * (ld(GE_G2Y, c1, c2) - e2y);
+        }
+    }
+    // e_a(q + c_a) - e_a(q - c_a)
+    __device__ __forceinline__ void dS(int a, T &dx, T &dy) const
+    {
+        const int c1 = cx(a), c2 = cy(a);
+        dx = 0.f;
+        dy = 0.f;
+        if (c1 != 0) {
+            dx += (T)c1 * (ld(GE_G1X, c1, c2) - ld(GE_G1X, -c1, -c2));
+            dy += (T)c1 * (ld(GE_G1Y, c1, c2) - ld(GE_G1Y, -c1, -c2));
+        }
+        if (c2 != 0) {
+            dx += (T)c2 * (ld(GE_G2X, c1, c2) - ld(GE_G2X, -c1, -c2));
+            dy += (T)c2 * (ld(GE_G2Y, c1, c2) - ld(GE_G2Y, -c1, -c2));
+        }
+    }
+
+    __device__ __forceinline__ void setup(const InstDesc *__restrict__ d, const float *lds, const double (&ref)[GE_NF],
+                                          int wave, int lane, int row, int col)
+    {
+        L = lds;
+        o = (wave + CM) * TC + lane + CM;
+        i = row;
+        n1 = d->n1;
+        per1 = d->periodic1;
+        bclo = d->bc_lo;
+        bchi = d->bc_hi;
+        const double rho0 = d->rho0;
+        rho0f = (float)rho0;
+        kpi = (T)d->kpi;
+        e1x = ld(GE_G1X, 0, 0);
+        e1y = ld(GE_G1Y, 0, 0);
+        e2x = ld(GE_G2X, 0, 0);
+        e2y = ld(GE_G2Y, 0, 0);
+        eJ = ld(GE_J, 0, 0);
+        e11 = ld(GE_H11, 0, 0);
+        e12 = ld(GE_H12, 0, 0);
+        e22 = ld(GE_H22, 0, 0);
+        r12 = (float)ref[GE_H12];
+        // the cell's own values, once per cell in FP64
+        const double g1x = ref[GE_G1X] + e1x, g1y = ref[GE_G1Y] + e1y;
+        const double g2x = ref[GE_G2X] + e2x, g2y = ref[GE_G2Y] + e2y;
+        const double J = ref[GE_J] + eJ, H11 = ref[GE_H11] + e11, H12 = ref[GE_H12] + e12, H22 = ref[GE_H22] + e22;
+        const double iJ = 1.0 / J;
+        G11 = (T)(H11 * iJ);
+        G12 = (T)(H12 * iJ);
+        G22 = (T)(H22 * iJ);
+        // co-tangents g^1 = (g_2 x z) / J, g^2 = (z x g_1) / J
+        u1x = (T)(g2y * iJ);
+        u1y = (T)(-g2x * iJ);
+        u2x = (T)(-g1y * iJ);
+        u2y = (T)(g1x * iJ);
+        mb = (T)(rho0 * J);
+        // the base's share of the force sum, sum_a (A+_a + A+_-a) B_a, sums
+        // products of population-size bases: formed in FP64 when the grid is
+        // created, read from the grid's per-cell table
+        const T *tab = (const T *)d->tab + (size_t)row * d->n2 + col;
+        c1s = tab[(size_t)TB::C1 * d->ncell];
+        c2s = tab[(size_t)TB::C2 * d->ncell];
+    }
+
+    // rest equilibrium phi_rest,a(g^ij)
+    __device__ __forceinline__ T rest(int a) const
+    {
+        const T c1 = (T)cx(a), c2 = (T)cy(a);
+        const T cGc = c1 * c1 * G11 + (T)2 * c1 * c2 * G12 + c2 * c2 * G22;
+        return (T)weight<Q>(a) *
+               ((T)1 + (cGc - (c1 * c1 + c2 * c2) - (T)T0 * (G11 + G22 - (T)2)) * (T)(1.0 / (2.0 * T0)));
+    }
+    // odd equilibrium coefficient K_a = w_a (c.G.c - T0 tr G) / (2 T0^2)
+    __device__ __forceinline__ T kodd(int a) const
+    {
+        const T c1 = (T)cx(a), c2 = (T)cy(a);
+        const T cGc = c1 * c1 * G11 + (T)2 * c1 * c2 * G12 + c2 * c2 * G22;
+        return (T)(weight<Q>(a) / (2.0 * T0 * T0)) * (cGc - (T)T0 * (G11 + G22));
+    }
+    // storage base of the pulled source (its local rest state), moved to
+    // this cell's compute base: rho0 (J phi_rest,a at the source - at this
+    // cell), linear in the differences of J and H (the q1 component of c_a
+    // flipped at a moving wall flips the sign of the source's c1 c2 H12 term)
+    __device__ __forceinline__ T dbase(int a) const
+    {
+        const int ti = i - cx(a);
+        const bool lo = ti < 0, hi = ti >= n1;
+        int dr = -cx(a);
+        bool flip = false;
+        if (!per1 && (lo || hi)) {
+            // mirror image across the wall: source row r, direction reversed
+            // (no-slip) or with its q1 component flipped (moving)
+            const int r = lo ? -1 - ti : 2 * n1 - 1 - ti;
+            dr = r - i;
+            flip = (lo ? bclo : bchi) != BC_NOSLIP;
+        }
+        const int dc = -cy(a);
+        const T c1 = (T)cx(a), c2 = (T)cy(a);
+        const T dJ = ld(GE_J, dr, dc) - eJ;
+        const T d11 = ld(GE_H11, dr, dc) - e11;
+        const T d22 = ld(GE_H22, dr, dc) - e22;
+        const T d12 = flip ? -(ld(GE_H12, dr, dc) + e12) - (T)2 * r12 : ld(GE_H12, dr, dc) - e12;
+        return rho0f * (T)weight<Q>(a) *
+               ((T)(2.0 - (cx(a) * cx(a) + cy(a) * cy(a)) / (2.0 * T0)) * dJ +
+                (c1 * c1 * d11 + (T)2 * c1 * c2 * d12 + c2 * c2 * d22 - (T)T0 * (d11 + d22)) * (T)(1.0 / (2.0 * T0)));
+    }
+    // compute base minus storage base: both the local rest state
+    __device__ __forceinline__ T sbdiff(int) const { return (T)0; }
+
+    __device__ __forceinline__ T operator()(int f) const
+    {
+        if (f == TB::G11) return G11;
+        if (f == TB::G12) return G12;
+        if (f == TB::G22) return G22;
+        if (f == TB::MB) return mb;
+        if (f == TB::C1) return c1s;
+        if (f == TB::C2) return c2s;
+        if (f == TB::D0) return (T)0;
+        if (f == TB::PHIB0) return rest(0);
+        if (f < TB::PB(0)) {
+            const int a = (f - 8) / 3 + 1, k = (f - 8) % 3;
+            if (k == 2) return dbase(a);
+            T dx, dy;
+            dA(a, dx, dy);
+            return k == 0 ? dx * u1x + dy * u1y : dx * u2x + dy * u2y;
+        }
+        if (f < TB::SB(0)) {
+            const int p = (f - TB::PB(0)) / 6, k = (f - TB::PB(0)) % 6;
+            const int a = pair_rep(p);
+            if (k == 0) return kodd(a);
+            if (k == 1) return (T)0;
+            if (k == 2) return rest(a);
+            T sx, sy;
+            dS(a, sx, sy);
+            const T S1 = sx * u1x + sy * u1y, S2 = sx * u2x + sy * u2y;
+            const T c1 = (T)cx(a), c2 = (T)cy(a);
+            if (k == 3) return kpi * c1 * S1;
+            if (k == 4) return kpi * (c1 * S2 + c2 * S1);
+            return kpi * c2 * S2;
+        }
+        return sbdiff(f - TB::SB(0));
+    }
+};
+
+// Rebuilt table fields for FP64 compute (the particle numbers themselves,
+// no offset base), from the staged FP64 tangents.
+template <int Q, typename T>
+struct GeoTab {
+    static_assert(sizeof(T) == 8, "FP32 compute uses GeoTabF");
+    using TB = Tab<Q>;
+    static constexpr int CM = cmax<Q>();
+    static constexpr double T0 = lattice_T0<Q>();
     static constexpr int TC = geo_tile_cols<Q>(), FS = geo_tile_field<Q>();
     const double *L;   // staged geometry
     int o;             // own cell in a staged field
-    int i, n1, per1, bclo, bchi, sbase;
-    double g1x, g1y, g2x, g2y, J, h11, h12, h22, rho0;
-    T u1x, u1y, u2x, u2y, G11, G12, G22, mb, c1s, c2s, kpi;
+    double g1x, g1y, g2x, g2y;
+    T u1x, u1y, u2x, u2y, G11, G12, G22, kpi;
 
     __device__ __forceinline__ double ld(int f, int dr, int dc) const { return L[o + (f * FS + dr * TC + dc)]; }
 
@@ -410,60 +627,26 @@ struct GeoTab {
         }
     }
 
-    __device__ __forceinline__ void setup(const InstDesc *__restrict__ d, const double *lds, int wave, int lane, int row,
-                                          int col)
+    __device__ __forceinline__ void setup(const InstDesc *__restrict__ d, const double *lds, int wave, int lane, int,
+                                          int)
     {
         L = lds;
         o = (wave + CM) * TC + lane + CM;
-        i = row;
-        n1 = d->n1;
-        per1 = d->periodic1;
-        bclo = d->bc_lo;
-        bchi = d->bc_hi;
-        sbase = d->sbase;
-        rho0 = d->rho0;
         kpi = (T)d->kpi;
         g1x = ld(GE_G1X, 0, 0);
         g1y = ld(GE_G1Y, 0, 0);
         g2x = ld(GE_G2X, 0, 0);
         g2y = ld(GE_G2Y, 0, 0);
-        double iJ;
-        if constexpr (CB) {
-            J = ld(GE_J, 0, 0);
-            h11 = ld(GE_H11, 0, 0);
-            h12 = ld(GE_H12, 0, 0);
-            h22 = ld(GE_H22, 0, 0);
-            iJ = 1.0 / J;
-            G11 = (T)(h11 * iJ);
-            G12 = (T)(h12 * iJ);
-            G22 = (T)(h22 * iJ);
-        } else {
-            J = g1x * g2y - g1y * g2x;
-            iJ = 1.0 / J;
-            const double iJ2 = iJ * iJ;
-            h11 = h12 = h22 = 0.0;
-            G11 = (T)((g2x * g2x + g2y * g2y) * iJ2);
-            G12 = (T)(-(g1x * g2x + g1y * g2y) * iJ2);
-            G22 = (T)((g1x * g1x + g1y * g1y) * iJ2);
-        }
+        const double J = g1x * g2y - g1y * g2x;
+        const double iJ = 1.0 / J, iJ2 = iJ * iJ;
+        G11 = (T)((g2x * g2x + g2y * g2y) * iJ2);
+        G12 = (T)(-(g1x * g2x + g1y * g2y) * iJ2);
+        G22 = (T)((g1x * g1x + g1y * g1y) * iJ2);
         // co-tangents g^1 = (g_2 x z) / J, g^2 = (z x g_1) / J
-        const double v1x = g2y * iJ, v1y = -g2x * iJ, v2x = -g1y * iJ, v2y = g1x * iJ;
-        u1x = (T)v1x;
-        u1y = (T)v1y;
-        u2x = (T)v2x;
-        u2y = (T)v2y;
-        mb = (T)0;
-        c1s = (T)0;
-        c2s = (T)0;
-        if constexpr (CB) {
-            // the base's share of the force sum, sum_a (A+_a + A+_-a) B_a,
-            // sums products of population-size bases: formed in FP64 when the
-            // grid is created, read from the grid's per-cell table
-            mb = (T)(rho0 * J);
-            const T *tab = (const T *)d->tab + (size_t)row * d->n2 + col;
-            c1s = tab[(size_t)TB::C1 * d->ncell];
-            c2s = tab[(size_t)TB::C2 * d->ncell];
-        }
+        u1x = (T)(g2y * iJ);
+        u1y = (T)(-g2x * iJ);
+        u2x = (T)(-g1y * iJ);
+        u2y = (T)(g1x * iJ);
     }
 
     // rest equilibrium phi_rest,a(g^ij)
@@ -481,63 +664,17 @@ struct GeoTab {
         const T cGc = c1 * c1 * G11 + (T)2 * c1 * c2 * G12 + c2 * c2 * G22;
         return (T)(weight<Q>(a) / (2.0 * T0 * T0)) * (cGc - (T)T0 * (G11 + G22));
     }
-    // storage base of the pulled source, moved to this cell's compute base
-    __device__ __forceinline__ T dbase(int a) const
-    {
-        if constexpr (!CB) {
-            return (T)0;
-        } else {
-            const int ti = i - cx(a);
-            const bool lo = ti < 0, hi = ti >= n1;
-            int dr = -cx(a);
-            double s = 1.0;
-            if (!per1 && (lo || hi)) {
-                // mirror image across the wall: source row r, direction
-                // reversed (no-slip) or with its q1 component flipped (moving)
-                const int r = lo ? -1 - ti : 2 * n1 - 1 - ti;
-                dr = r - i;
-                if ((lo ? bclo : bchi) != BC_NOSLIP) s = -1.0;
-            }
-            const int dc = -cy(a);
-            // storage base of the source: local rest state, J w rho0, or none
-            double Bs = 0.0;
-            if (sbase == 0) {
-                Bs = jrest<Q>(a, ld(GE_J, dr, dc), ld(GE_H11, dr, dc), ld(GE_H12, dr, dc), ld(GE_H22, dr, dc), s);
-            } else if (sbase == 1) {
-                Bs = weight<Q>(a) * ld(GE_J, dr, dc);
-            }
-            return (T)(rho0 * (Bs - jrest<Q>(a, J, h11, h12, h22)));
-        }
-    }
-    // compute base minus storage base (added to a computed offset to store
-    // it): rho0 (J phi_rest,a - B_a) with J phi_rest,a = J rest(a) (the rest
-    // equilibrium at this cell's G) and B_a = w_a J rho0 or 0, in the compute
-    // type from mb = rho0 J: FP64 here would keep 21 FP64 values live through
-    // the store and cost the kernel half its occupancy
-    __device__ __forceinline__ T sbdiff(int a) const
-    {
-        if constexpr (!CB) {
-            return (T)0;
-        } else {
-            if (sbase == 0) return (T)0;
-            const T jr = mb * rest(a);
-            return sbase == 1 ? jr - (T)weight<Q>(a) * mb : jr;
-        }
-    }
 
     __device__ __forceinline__ T operator()(int f) const
     {
         if (f == TB::G11) return G11;
         if (f == TB::G12) return G12;
         if (f == TB::G22) return G22;
-        if (f == TB::MB) return mb;
-        if (f == TB::C1) return c1s;
-        if (f == TB::C2) return c2s;
-        if (f == TB::D0) return CB ? (T)0 : rest(0);
-        if (f == TB::PHIB0) return CB ? rest(0) : (T)0;
+        if (f == TB::MB || f == TB::C1 || f == TB::C2 || f == TB::PHIB0) return (T)0;
+        if (f == TB::D0) return rest(0);
         if (f < TB::PB(0)) {
             const int a = (f - 8) / 3 + 1, k = (f - 8) % 3;
-            if (k == 2) return dbase(a);
+            if (k == 2) return (T)0;   // no offset base
             double dx, dy;
             dA(a, dx, dy);
             return k == 0 ? (T)dx * u1x + (T)dy * u1y : (T)dx * u2x + (T)dy * u2y;
@@ -546,8 +683,8 @@ struct GeoTab {
             const int p = (f - TB::PB(0)) / 6, k = (f - TB::PB(0)) % 6;
             const int a = pair_rep(p);
             if (k == 0) return kodd(a);
-            if (k == 1) return CB ? (T)0 : rest(a);
-            if (k == 2) return CB ? rest(a) : (T)0;
+            if (k == 1) return rest(a);
+            if (k == 2) return (T)0;
             double sx, sy;
             dS(a, sx, sy);
             const T S1 = (T)sx * u1x + (T)sy * u1y, S2 = (T)sx * u2x + (T)sy * u2y;
@@ -556,7 +693,7 @@ struct GeoTab {
             if (k == 4) return kpi * (c1 * S2 + c2 * S1);
             return kpi * c2 * S2;
         }
-        return sbdiff(f - TB::SB(0));
+        return (T)0;   // storage base differences: none
     }
 };
 
@@ -585,7 +722,7 @@ struct TabSel {
 };
 template <int Q, typename T>
 struct TabSel<Q, T, 2> {
-    using type = GeoTab<Q, T>;
+    using type = typename std::conditional<sizeof(T) == 4, GeoTabF<Q>, GeoTab<Q, T>>::type;
 };
 
 // ---------------------------------------------------------------------------
@@ -595,10 +732,25 @@ struct TabSel<Q, T, 2> {
 // the staged geometry.
 // ---------------------------------------------------------------------------
 
+// Per-lane base terms of the pulled populations (per-cell tables or rebuilt
+// fields): the source's storage base moved to this cell's compute base, added
+// once every pull is in flight.
+template <int Q, typename T, int CT, typename TBT>
+__device__ __forceinline__ void add_bases(const TBT &tb, T (&n)[Q])
+{
+    using TB = Tab<Q>;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
+        sgroup<CT>();
+    }
+    phase_fence<CT>();
+}
+
 // Pulled populations N_a(i, j) of Eq. (adv) with the boundary sources of
 // App. B, read from the post-collision field in HBM and moved to the cell's
 // compute base.  j0 is the first column of the wave's 64.
-template <int Q, typename T, typename S, int CT, bool WIDE, typename TBT>
+template <int Q, typename T, typename S, int CT, bool WIDE, bool BASES = true, typename TBT>
 __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const TBT &tb, int i, int j, int j0, int pin,
                                           T (&n)[Q])
 {
@@ -707,15 +859,8 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
             n[a] = v;
         }
     }
-    if constexpr (CT != 0) {
-        // per-lane base terms once every pull is in flight
-#pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
-            sgroup<CT>();
-        }
-    }
-    phase_fence<CT>();
+    if constexpr (CT != 0 && BASES) add_bases<Q, T, CT>(tb, n);
+    if constexpr (CT == 0 || BASES) phase_fence<CT>();
 }
 
 // what the store and the moments pass need besides the post-collision values
@@ -925,14 +1070,10 @@ __device__ __forceinline__ void store_cell(const InstDesc *__restrict__ d, const
         }
     };
     if constexpr (CT == 2) {
-        // rebuilt fields with the storage base equal to the compute base (the
-        // local rest state) need no per-direction base terms: a loop without
-        // them keeps those FP32 values from being held live through the store
-        // (measured: 113 instead of 256 + 88 registers in FP32)
-        if (tb.sbase == 0)
-            store_all(std::false_type{});
-        else
-            store_all(std::true_type{});
+        // rebuilt fields: the storage base is the compute base (the local
+        // rest state, or none in FP64), so the store needs no per-direction
+        // base terms
+        store_all(std::false_type{});
     } else {
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
@@ -1011,44 +1152,66 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int i = tl.y + wave;
     const int n1 = d->n1, n2 = d->n2;
-    const double *geo_lds = nullptr;
-    if constexpr (CT == 2) {
-        if (tl.y >= n1) return;   // padding tile (the whole workgroup)
-        geo_lds = stage_geometry<Q, T>(d, tl, wave);
-    }
-    if (i >= n1) return;
     const int j0 = tl.z;
     const int j = j0 + (int)(threadIdx.x & 63);
-    if (j >= n2) return;
     const int pin = (par ^ d->par0) & 1;
 
-    typename TabSel<Q, T, CT>::type tb;
-    if constexpr (CT == 2) {
-        tb.setup(d, geo_lds, wave, j - j0, i, j);
-    } else if constexpr (CT == 1) {
-        tb.p = (const T *)d->tab + (size_t)i * n2 + j;
-        tb.s = d->ncell;
-    } else {
-        tb.p = (const T *)d->tab + (size_t)i * TB::STRIDE;
-        tb.s = 1;
-    }
-
-    T n[Q], s[Q];
-    pull_cell<Q, T, S, CT, WIDE>(d, tb, i, j, j0, pin, n);
-
-    T Lo1, Lo2;
-    if constexpr (MOM && CT == 0) {
-        own_lag_global<Q, T, S, WIDE>(d, tb, i, j, pin, Lo1, Lo2);
-    } else {
-        // lagged own-cell force sums, formed when the previous step produced
-        // N'(q, t-1)
+    // lagged own-cell force sums, formed when the previous step produced
+    // N'(q, t-1)
+    auto load_lag = [&](T &L1, T &L2) {
         constexpr uint32_t ET = sizeof(T);
         const uint32_t lsa_b = (uint32_t)d->lsa * ET;
         const __amdgpu_buffer_rsrc_t rlag = WIDE ? row_rsrc(d->lag[pin], (size_t)d->lsr * ET, i, 1)
                                                  : make_rsrc(d->lag[pin], 2 * (uint32_t)d->plane * ET);
         const uint32_t jt = (uint32_t)j * ET, rowt = WIDE ? 0u : (uint32_t)i * (uint32_t)d->lsr * ET;
-        Lo1 = bload<T, T>(rlag, jt, rowt);
-        Lo2 = bload<T, T>(rlag, jt, lsa_b + rowt);
+        L1 = bload<T, T>(rlag, jt, rowt);
+        L2 = bload<T, T>(rlag, jt, lsa_b + rowt);
+    };
+
+    typename TabSel<Q, T, CT>::type tb;
+    T n[Q], s[Q];
+    T Lo1, Lo2;
+    if constexpr (CT == 2) {
+        if (tl.y >= n1) return;   // padding tile (the whole workgroup)
+        const bool act = i < n1 && j < n2;
+        if constexpr (sizeof(T) == 8) {
+            // the geometry goes to LDS while the pulls and force sums, which
+            // need none of it, are loaded; every wave reaches the barrier
+            const double *geo_lds = stage_geometry<Q, T>(d, tl, wave);
+            if (act) {
+                pull_cell<Q, T, S, CT, WIDE, false>(d, tb, i, j, j0, pin, n);
+                load_lag(Lo1, Lo2);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (!act) return;
+            tb.setup(d, geo_lds, wave, j - j0, i, j);
+        } else {
+            double ref[GE_NF];
+            const float *geo_lds = stage_geometry_f<Q>(d, tl, wave, ref);
+            if (act) {
+                pull_cell<Q, T, S, CT, WIDE, false>(d, tb, i, j, j0, pin, n);
+                load_lag(Lo1, Lo2);
+            }
+            __syncthreads();
+            if (!act) return;
+            tb.setup(d, geo_lds, ref, wave, j - j0, i, j);
+        }
+        add_bases<Q, T, CT>(tb, n);
+    } else {
+        if (i >= n1 || j >= n2) return;
+        if constexpr (CT == 1) {
+            tb.p = (const T *)d->tab + (size_t)i * n2 + j;
+            tb.s = d->ncell;
+        } else {
+            tb.p = (const T *)d->tab + (size_t)i * TB::STRIDE;
+            tb.s = 1;
+        }
+        pull_cell<Q, T, S, CT, WIDE>(d, tb, i, j, j0, pin, n);
+        if constexpr (MOM && CT == 0)
+            own_lag_global<Q, T, S, WIDE>(d, tb, i, j, pin, Lo1, Lo2);
+        else
+            load_lag(Lo1, Lo2);
     }
 
     CellOut<T> o;

@@ -493,6 +493,10 @@ int lbm_grid_create(const lbm_grid_desc *desc, lbm_grid **out)
     if (hflag[1]) return bail(LBM_EINVAL, "the mapping has J <= 0 (or non-finite geometry) in some cell");
     g->row = (D.geometry != LBM_GEOM_AUTO) ? 0 : (hflag[0] ? 0 : 1);
     g->ct = g->row ? 0 : (D.geometry == LBM_GEOM_CELL_TABLE ? 1 : 2);
+    // offset storage with a base other than the local rest state shifts every
+    // pulled value by base differences the rebuilt FP32 terms carry only to a
+    // few 1e-6: such grids read the stored table instead
+    if (g->ct == 2 && g->precision != LBM_FP64 && D.offset_base != LBM_BASE_LOCAL_REST) g->ct = 1;
     g->nent = g->row ? n1 : nc;
     const int nfe = g->precision == LBM_FP64 ? (int)GE_J : (int)GE_NF;
     const size_t gfs = (size_t)(n1 + 2 * cm) * (n2 + 2 * cm);
