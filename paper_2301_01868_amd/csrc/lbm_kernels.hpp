@@ -1239,8 +1239,8 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
 // table holds (instance, first row, first column, lattice).  WIDE instances
 // serve population buffers of 2 GiB and more.
 template <int Q, typename T, typename S, int CT, bool MOM, bool ITER, bool WIDE>
-__global__ __launch_bounds__(256) void k_step(const InstDesc *__restrict__ insts, const int4 *__restrict__ tiles,
-                                              int par)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CT == 2 && sizeof(T) == 4 && Q == 21 ? 4 : 1)))
+void k_step(const InstDesc *__restrict__ insts, const int4 *__restrict__ tiles, int par)
 {
     step_tile<Q, T, S, CT, MOM, ITER, WIDE>(insts, tiles[blockIdx.x], par);
 }
