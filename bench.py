@@ -39,26 +39,30 @@ STEP_SOURCES = ["paper_2301_01868_amd/csrc/lbm_kernels.hpp", "paper_2301_01868_a
                 "paper_2301_01868_amd/csrc/lbm_lib.hip", "paper_2301_01868_amd/build.py"]
 
 
-def step_source_hash():
+def step_source_hash(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for f in STEP_SOURCES:
+    for f in sources or STEP_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def recorded_traffic(workload, prec_name, cells):
+STEP3_SOURCES = ["paper_2301_01868_amd/csrc/lbm3d_kernels.hpp", "paper_2301_01868_amd/csrc/lbm3d_lattice.hpp",
+                 "paper_2301_01868_amd/csrc/lbm3d_lib.hip", "paper_2301_01868_amd/build.py"]
+
+
+def recorded_traffic(workload, prec_name, cells, kernel="k_step", sources=None):
     """HBM bytes per launch of the dominant kernel from the committed counter
     record (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
     calibration), or None when there is no record for this launch or the
     kernel's sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "k_step_%s_traffic.json" % workload)
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha256") != step_source_hash():
+    if rec.get("source_sha256") != step_source_hash(sources or STEP_SOURCES):
         return None
     e = rec.get("launches", {}).get(prec_name)
     if not e or e.get("cells") != cells:
@@ -264,13 +268,16 @@ def measure3d(steps, warmup, stream):
     cells = case.ncell
     alg = 2 * 39 * 8 * cells          # one read and one write of every FP64 population
     achieved = alg / (ms / steps * 1e-3) / 1e9
+    traffic = recorded_traffic("cylinder_couette_128x512x64", "f64", cells, kernel="k_step3", sources=STEP3_SOURCES)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_step3 (D3Q39, f64)", "bytes_per_launch": alg,
+            "avg_launch_us": round(ms / steps * 1e3, 3)}
+    if traffic:
+        roof["traffic_GBps"] = round(traffic / (ms / steps * 1e-3) / 1e9, 1)
     return {"value": round(cells * steps / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(ms / steps, 5), "cells": cells, "bad_cells_after": bad,
-            "workload": "cylinder_couette_128x512x64 (D3Q39, FP64)",
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                         "kernel": "k_step3 (D3Q39, f64)", "bytes_per_launch": alg,
-                         "avg_launch_us": round(ms / steps * 1e3, 3)}}
+            "workload": "cylinder_couette_128x512x64 (D3Q39, FP64)", "roofline": roof}
 
 
 def main():
