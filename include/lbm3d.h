@@ -62,8 +62,9 @@ int lbm3d_lattice(int32_t *c, double *w, double *T0);
  * per-row tables, double-buffered populations.  Errors: LBM_EINVAL (sizes,
  * n1 < 3 with walls, halo < 4, tau <= 1/2, unpaired periodic side, unknown
  * boundary kind, J <= 0 or non-finite geometry, metric terms that depend on
- * q2 or q3, or populations beyond 2^31 elements per buffer), LBM_ENOMEM,
- * LBM_EDEVICE. */
+ * q2 or q3, populations beyond 2^31 elements per buffer, or 7 rows i of
+ * populations (n2 x 39 x n3 rounded up to 64, FP64) of 4 GiB or more),
+ * LBM_ENOMEM, LBM_EDEVICE. */
 int lbm3d_grid_create(const lbm3d_grid_desc *desc, lbm3d_grid **out);
 void lbm3d_grid_destroy(lbm3d_grid *g);
 const char *lbm3d_last_error(const lbm3d_grid *g);

@@ -193,14 +193,14 @@ __device__ __forceinline__ void eq_coeffs(const double G[6], const double U[3], 
             constexpr int y = decltype(Y)::value;
             const double a2 = (G[sym2(x, y)] - (x == y ? 1.0 : 0.0)) * T0 + Ut[x] * Ut[y];
             if constexpr (x == y) trA2 += a2;
-            K[4 + sym2(x, y)] = mult(4 + sym2(x, y)) * a2 / (2.0 * T0 * T0);
+            K[4 + sym2(x, y)] = a2 * (mult(4 + sym2(x, y)) / (2.0 * T0 * T0));
             sfor<y, 3>([&](auto Z) {
                 constexpr int z = decltype(Z)::value;
                 const double b3 = T0 * ((G[sym2(x, y)] * Ut[z] - (x == y ? U[z] : 0.0)) +
                                         (G[sym2(y, z)] * Ut[x] - (y == z ? U[x] : 0.0)) +
                                         (G[sym2(z, x)] * Ut[y] - (z == x ? U[y] : 0.0))) +
                                   Ut[x] * Ut[y] * Ut[z];
-                K[10 + sym3(x, y, z)] = mult(10 + sym3(x, y, z)) * b3 / (6.0 * T0 * T0 * T0);
+                K[10 + sym3(x, y, z)] = b3 * (mult(10 + sym3(x, y, z)) / (6.0 * T0 * T0 * T0));
                 // V^w = sum_v B3^wvv: this (x, y, z) contributes where two indices agree
                 if constexpr (x == y && y == z) V[x] += b3;
                 else if constexpr (x == y) V[z] += b3;
@@ -208,10 +208,10 @@ __device__ __forceinline__ void eq_coeffs(const double G[6], const double U[3], 
             });
         });
     });
-    K[0] = 1.0 - trA2 / (2.0 * T0);
+    K[0] = 1.0 - trA2 * (1.0 / (2.0 * T0));
     sfor<0, 3>([&](auto X) {
         constexpr int x = decltype(X)::value;
-        K[1 + x] = U[x] / T0 - V[x] / (2.0 * T0 * T0);
+        K[1 + x] = U[x] * (1.0 / T0) - V[x] * (1.0 / (2.0 * T0 * T0));
     });
 }
 template <int A>
@@ -240,17 +240,29 @@ __global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int 
 
     // ---- pull (Eq. adv, App. B) ----
     double n[Q];
-    const bool nearwall = !d->periodic1 && (c.i < CMAX || c.i >= d->n1 - CMAX);
-    if (!nearwall) {
-        // every source row lies inside the grid (or wraps along a periodic q1)
+    if (c.i >= CMAX && c.i < d->n1 - CMAX) {
+        // rows i - c_max .. i + c_max, all inside the grid: one buffer
+        // resource based at row i - c_max; the wave's 64 cells share (i, j),
+        // so a direction's source offset is a scalar part (row, wrapped j,
+        // direction) plus one of 2 c_max + 1 per-lane k offsets (wrapped
+        // along the periodic q3)
+        const int n2 = d->n2, pitch = d->pitch;
+        const size_t plane_b = (size_t)n2 * Q * pitch * sizeof(double);   // one row i
+        const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((const char *)P + (size_t)(c.i - CMAX) * plane_b), (short)0, (int)(uint32_t)((2 * CMAX + 1) * plane_b),
+            0x00020000);
+        uint32_t vk[2 * CMAX + 1];
+#pragma unroll
+        for (int s = -CMAX; s <= CMAX; ++s) vk[s + CMAX] = (uint32_t)wrap3(c.k - s, d->n3) * (uint32_t)sizeof(double);
         sfor<0, Q>([&](auto Aic) {
             constexpr int a = decltype(Aic)::value;
-            int r = c.i - cvec(a, 0);
-            if (d->periodic1) r = wrap3(r, d->n1);
-            const int jj = wrap3(c.j - cvec(a, 1), d->n2), kk = wrap3(c.k - cvec(a, 2), d->n3);
-            n[a] = P[pidx3(d->n2, d->pitch, r, jj, a, kk)];
+            const int jj = wrap3(c.j - cvec(a, 1), n2);
+            const uint32_t soff =
+                (uint32_t)((((CMAX - cvec(a, 0)) * n2 + jj) * Q + a) * pitch) * (uint32_t)sizeof(double);
+            n[a] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rin, vk[cvec(a, 2) + CMAX], soff, 2));
         });
     } else {
+        // rows at a wall (mirror sources, App. B) or at a periodic q1 wrap
         sfor<0, Q>([&](auto Aic) {
             constexpr int a = decltype(Aic)::value;
             int r, beta, wall;
@@ -351,7 +363,8 @@ __global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int 
                     });
                 }
             });
-            const double dN = weight(a) * (t1 / T0 + (t2 / T0 - trPi) / T0);
+            // the constants fold at compile time: no division per direction
+            const double dN = (weight(a) / T0) * (t1 - trPi) + (weight(a) / (T0 * T0)) * t2;
             const double mp = m * phi_poly<a>(K);
             const double np = n[a] - (n[a] - mp) * d->omega + dN;
             Pout[pidx3(d->n2, d->pitch, c.i, c.j, a, c.k)] = np;

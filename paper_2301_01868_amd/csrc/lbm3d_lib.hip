@@ -104,6 +104,9 @@ int lbm3d_grid_create(const lbm3d_grid_desc *desc, lbm3d_grid **out)
     const long long pitch = D.n3 >= 64 ? (D.n3 + 63) / 64 * 64 : D.n3;
     if ((long long)D.n1 * D.n2 * Q * pitch >= (1LL << 31) || (long long)D.n1 * D.n2 * ((D.n3 + 63) / 64) >= (1LL << 31))
         return fail3(nullptr, LBM_EINVAL, "grid too large");
+    // the step addresses 2 c_max + 1 rows i of populations through one buffer resource (32-bit offsets)
+    if ((2LL * CMAX + 1) * D.n2 * Q * pitch * 8 >= (1LL << 32))
+        return fail3(nullptr, LBM_EINVAL, "rows too large: 7 rows of populations must stay below 4 GiB");
 
     lbm3d_grid *g = new lbm3d_grid();
     g->n1 = D.n1;
