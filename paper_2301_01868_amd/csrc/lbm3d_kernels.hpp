@@ -214,6 +214,23 @@ __device__ __forceinline__ void eq_coeffs(const double G[6], const double U[3], 
         K[1 + x] = U[x] * (1.0 / T0) - V[x] * (1.0 / (2.0 * T0 * T0));
     });
 }
+// the even (degree 0 and 2) and odd (degree 1 and 3) parts of sum_k K_k P_k(c_A):
+// phi_A = w_A (E + O) and phi_-A = w_A (E - O)
+template <int A>
+__device__ __forceinline__ void phi_parts(const double K[NK], double &E, double &O)
+{
+    E = 0.0;
+    O = 0.0;
+    sfor<0, NK>([&](auto Kc) {
+        constexpr int k = decltype(Kc)::value;
+        constexpr int p = mono(k, cvec(A, 0), cvec(A, 1), cvec(A, 2));
+        constexpr bool odd = (k >= 1 && k < 4) || k >= 10;
+        if constexpr (p != 0) {
+            if constexpr (odd) O += (double)p * K[k];
+            else E += (double)p * K[k];
+        }
+    });
+}
 template <int A>
 __device__ __forceinline__ double phi_poly(const double K[NK])
 {
@@ -350,8 +367,24 @@ __global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int 
         // ---- correction, BGK, store; the next step's lagged force sums ----
         double *__restrict__ Pout = d->P[pin ^ 1];
         double Ln[3] = {0.0, 0.0, 0.0};
-        sfor<0, Q>([&](auto Aic) {
+        // the rest direction, then the pairs (a, -a) = (2p - 1, 2p): the even and
+        // odd parts of the equilibrium polynomial, c.JF and c c : dPi are formed
+        // once per pair (the odd ones flip sign for -a)
+        auto store = [&](auto Aic, double mp, double dN) {
             constexpr int a = decltype(Aic)::value;
+            const double np = n[a] - (n[a] - mp) * d->omega + dN;
+            Pout[pidx3(d->n2, d->pitch, c.i, c.j, a, c.k)] = np;
+            if constexpr (a > 0) {
+                Ln[0] += tb[6 + 3 * a + 0] * np;
+                Ln[1] += tb[6 + 3 * a + 1] * np;
+                Ln[2] += tb[6 + 3 * a + 2] * np;
+            }
+        };
+        store(std::integral_constant<int, 0>{}, m * phi_poly<0>(K), -(weight(0) / T0) * trPi);
+        __builtin_amdgcn_sched_barrier(0);
+        sfor<1, (Q + 1) / 2>([&](auto Pc) {
+            constexpr int a = 2 * decltype(Pc)::value - 1, b = a + 1;
+            static_assert(opp(a) == b, "pairs (2p - 1, 2p)");
             double t1 = 0.0, t2 = 0.0;
             sfor<0, 3>([&](auto X) {
                 constexpr int x = decltype(X)::value;
@@ -363,18 +396,15 @@ __global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int 
                     });
                 }
             });
+            double E, O;
+            phi_parts<a>(K, E, O);
+            const double mw = m * weight(a);
             // the constants fold at compile time: no division per direction
-            const double dN = (weight(a) / T0) * (t1 - trPi) + (weight(a) / (T0 * T0)) * t2;
-            const double mp = m * phi_poly<a>(K);
-            const double np = n[a] - (n[a] - mp) * d->omega + dN;
-            Pout[pidx3(d->n2, d->pitch, c.i, c.j, a, c.k)] = np;
-            if constexpr (a > 0) {
-                Ln[0] += tb[6 + 3 * a + 0] * np;
-                Ln[1] += tb[6 + 3 * a + 1] * np;
-                Ln[2] += tb[6 + 3 * a + 2] * np;
-            }
-            // one direction at a time: without this boundary the scheduler
-            // starts every direction's arithmetic at once and runs out of registers
+            const double dNe = (weight(a) / (T0 * T0)) * t2 - (weight(a) / T0) * trPi, dNo = (weight(a) / T0) * t1;
+            store(std::integral_constant<int, a>{}, mw * (E + O), dNe + dNo);
+            store(std::integral_constant<int, b>{}, mw * (E - O), dNe - dNo);
+            // one pair at a time: without this boundary the scheduler starts
+            // every direction's arithmetic at once and runs out of registers
             __builtin_amdgcn_sched_barrier(0);
         });
         d->lag[pin ^ 1][lrow] = Ln[0];
