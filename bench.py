@@ -301,6 +301,8 @@ def main():
     ap.add_argument("--cal-requests", type=int, default=48)
     ap.add_argument("--cal-seconds", type=float, default=20.0)
     ap.add_argument("--seq-sample", type=int, default=4, help="requests replayed sequentially in FP64")
+    ap.add_argument("--fp64-above", type=float, default=None, metavar="STEPS",
+                    help="serve requests whose slowest decay time exceeds STEPS with FP64 populations")
     ap.add_argument("--no-sequential", action="store_true",
                     help="serving: skip the sequential FP64 replay (long traces)")
     ap.add_argument("--geometry", default="auto", choices=["auto", "cell", "cell_table"],
@@ -458,7 +460,8 @@ def serve_bench(args):
     mean_lu = serve.mean_predicted_lu(n_min=16, n_max=512, tol=tol)
     # 1. batched capacity on this request mix
     cal = serve.make_trace(seed=2301_01870, rate=1e9, n_requests=args.cal_requests, tol=tol)
-    srv = serve.Server(hbm_budget=budget, check_every=256, stream=stream, setup_stream=setup)
+    srv = serve.Server(hbm_budget=budget, check_every=256, stream=stream, setup_stream=setup,
+                       fp64_above=args.fp64_above)
     note("capacity run: %d requests for %.0f s" % (len(cal), args.cal_seconds))
     st = srv.run(cal, realtime=False, stop_after=args.cal_seconds, progress=note)
     capacity = st["lattice_updates"] / st["makespan"]
@@ -467,7 +470,8 @@ def serve_bench(args):
     rate = args.rate if args.rate > 0 else args.load * capacity / mean_lu
     trace = serve.make_trace(seed=2301_01869, rate=rate, n_requests=args.requests, tol=tol)
     base = copy.deepcopy(trace)
-    srv = serve.Server(hbm_budget=budget, check_every=256, stream=stream, setup_stream=setup)
+    srv = serve.Server(hbm_budget=budget, check_every=256, stream=stream, setup_stream=setup,
+                       fp64_above=args.fp64_above)
     note("served trace: %d requests at %.4g per s" % (len(trace), rate))
     info = srv.run(trace, realtime=True, progress=note)
     s_b = serve.summarize(trace, info["makespan"])
@@ -496,13 +500,16 @@ def serve_bench(args):
             a = trace[i]
             if a.status == "converged" and b.status == "converged":
                 diffs.append({"rid": i, "family": a.case.meta["draw"]["family"], "N": a.case.n1, "q": a.case.q,
-                              "tau": round(a.case.tau, 4), "steps_fp32": a.steps, "steps_fp64": b.steps,
+                              "tau": round(a.case.tau, 4), "served_precision": {0: "fp64", 1: "fp32", 2: "fp16"}.get(
+                                  a.precision, a.precision), "slowest_decay_steps": round(serve.slow_decay_steps(a.case)),
+                              "steps_served": a.steps, "steps_fp64": b.steps,
                               "max_diff_u_over_U": float(np.abs(a.result["u"] - b.result["u"]).max() / 0.05)})
     out = {"metric": "solves/s, p50/p99 latency (serving)", "value": round(s_b["solves_per_s"], 4),
            "unit": "solves/s", "higher_is_better": True, "data": "synthetic", "dtype": "f32",
            "config": {"workload": "poisson_trace_config5", "requests": len(trace), "rate_per_s": rate,
                       "n_wall_normal": "log-uniform 16..512, N x 4N cells", "tol": tol, "hbm_budget_bytes": budget,
-                      "check_every": 256},
+                      "check_every": 256, "fp64_above_decay_steps": args.fp64_above,
+                      "fp64_requests": sum(r.precision == lbm.LBM_FP64 for r in trace)},
            "offered_load": {"mean_predicted_lu_per_request": mean_lu, "offered_lu_per_s": rate * mean_lu,
                             "capacity_lu_per_s": capacity, "load_fraction": rate * mean_lu / capacity,
                             "stated_rate_per_s": 50.0, "stated_offered_lu_per_s": 50.0 * mean_lu,
@@ -512,7 +519,7 @@ def serve_bench(args):
                                              "peak_resident": st["peak_resident"]}},
            "batched_fp32": s_b, "sequential_fp64": seq,
            "capacity_over_sequential_lu_per_s": (capacity / seq["lu_per_s"]) if seq else None,
-           "fp32_vs_fp64": {"max_diff_u_over_U": max(d["max_diff_u_over_U"] for d in diffs) if diffs else None,
+           "served_vs_fp64": {"max_diff_u_over_U": max(d["max_diff_u_over_U"] for d in diffs) if diffs else None,
                             "requests": diffs}}
     print(json.dumps(out), flush=True)
 

@@ -53,6 +53,7 @@ class Request:
     best: float = math.inf        # lowest residual that halved the previous best
     best_step: int = 0            # step count at which `best` was reached
     admit_round: int = -1         # server round before which the request was admitted
+    precision: int = -1           # population storage the server chose
 
 
 def slow_decay_steps(case):
@@ -246,10 +247,15 @@ class Server:
     """Continuous batching of steady-state solves.  `stream` is the stream
     the batch runs on and `setup_stream` the one new grids are created on
     (torch.cuda.Stream objects; both made here when None).  `pool`: use the
-    torch caching allocator for grid memory."""
+    torch caching allocator for grid memory.  `fp64_above`: a slowest decay
+    time (steps) above which a request runs with FP64 populations instead of
+    `precision`: FP32 storage rounds the state every step, and for the
+    slowest mode that rounding adds up over its decay time, so slowly
+    converging solves need FP64 to keep their steady velocity within 1e-5 of
+    the speed scale (None: every request in `precision`)."""
 
     def __init__(self, hbm_budget=8 << 30, check_every=256, precision=lbm.LBM_FP32, max_steps=2_000_000,
-                 stream=None, stall_steps=200_000, setup_stream=None, pool=True):
+                 stream=None, stall_steps=200_000, setup_stream=None, pool=True, fp64_above=None):
         import torch
         self.budget = hbm_budget
         self.K = check_every
@@ -259,10 +265,17 @@ class Server:
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.setup_stream = setup_stream if setup_stream is not None else torch.cuda.Stream()
         self.pool = TorchPool(self.setup_stream) if pool else None
+        self.fp64_above = fp64_above
         self.stats = {}
 
+    def precision_of(self, r):
+        if self.fp64_above is not None and slow_decay_steps(r.case) > self.fp64_above:
+            return lbm.LBM_FP64
+        return self.precision
+
     def _admit(self, r, rounds, t0):
-        g = lbm.Grid(r.case, precision=self.precision, stream=_raw(self.setup_stream),
+        r.precision = self.precision_of(r)
+        g = lbm.Grid(r.case, precision=r.precision, stream=_raw(self.setup_stream),
                      alloc=None if self.pool is None else self.pool.desc)
         g.init()
         # queued set-up work stays ordered before the grid's first step
@@ -308,7 +321,7 @@ class Server:
                 now = ts - t0
                 while k < len(pending) and (not realtime or pending[k].arrival <= now):
                     r = pending[k]
-                    need = request_bytes(r.case, self.precision)
+                    need = request_bytes(r.case, self.precision_of(r))
                     if used + need > self.budget and (active or joined):
                         break
                     g = self._admit(r, rounds, t0)

@@ -41,3 +41,17 @@ def test_unstable_and_step_limit():
     assert serve.check_progress(r, SimpleNamespace(residual=1e-3, bad_cells=5), 10**9, 10**6) == "unstable"
     st, steps = _run([1e-3 * 0.5 ** (k / 5.0) for k in range(200)], max_steps=1000)
     assert (st, steps) == ("max_steps", 1000)
+
+
+def test_slow_solves_get_fp64_storage():
+    from paper_2301_01868_amd import lbm
+    srv = object.__new__(serve.Server)          # the policy alone: no streams or pool needed
+    srv.precision, srv.fp64_above = lbm.LBM_FP32, 10_000.0
+    fast = serve.Request(rid=0, arrival=0.0, case=G.planar_couette(9, G.faces_uniform(8), n2=4), tol=1e-8)
+    slow = serve.Request(rid=1, arrival=0.0, case=G.planar_couette(9, G.faces_uniform(256), n2=4), tol=1e-8)
+    assert serve.slow_decay_steps(fast.case) < 10_000 < serve.slow_decay_steps(slow.case)
+    assert srv.precision_of(fast) == lbm.LBM_FP32 and srv.precision_of(slow) == lbm.LBM_FP64
+    # admission charges the larger population buffers
+    assert serve.request_bytes(slow.case, lbm.LBM_FP64) > serve.request_bytes(slow.case, lbm.LBM_FP32)
+    srv.fp64_above = None
+    assert srv.precision_of(slow) == lbm.LBM_FP32
