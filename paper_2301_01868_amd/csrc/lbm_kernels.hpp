@@ -312,6 +312,30 @@ __host__ __device__ constexpr unsigned geo_stage_bytes()
     return (unsigned)(geo_stage_fields<T>() * geo_tile_field<Q>() * sizeof(T));
 }
 
+// Own-cell values by exchange.  The lagged force of Eq. (compo-constr) needs
+// the own cell's N'_a(q, t-1), which in this step is the value the neighbour
+// q + c_a pulls.  Steps of per-row-table D2Q9 grids take it from there: every
+// lane writes its pulled values, as loaded, to an LDS tile [wave][a - 1][lane]
+// of the workgroup's rows, and after a barrier each cell reads those of its
+// partners inside the tile; the rest (partners in another workgroup's rows or
+// columns, or outside the grid) are loaded from the own cell in HBM.  Either
+// way the value is the stored one, bit for bit, and the sum is formed in the
+// same order as the stored force sums of the other kernels, so the results
+// are the same bits.  (With c_max = 1 a 4-row tile finds 6.4 of the 8
+// partners inside; the 20 D2Q21 partners reach 3 rows out and keep the stored
+// sums.)
+template <int Q, typename S, int CT, bool MOM>
+__host__ __device__ constexpr bool xch_step()
+{
+    return CT == 0 && !MOM && Q == 9 && sizeof(S) >= 4;
+}
+// LDS bytes of the exchange tile of a workgroup of wpb waves
+template <int Q, typename T>
+__host__ __device__ constexpr unsigned xch_bytes(int wpb)
+{
+    return (unsigned)(wpb * (Q - 1) * 64 * (int)sizeof(T));
+}
+
 // Start copying the geometry of the workgroup's rows tl.y .. tl.y + wpb - 1
 // and columns tl.z .. tl.z + 63, with c_max layers around them, into the LDS
 // tile.  The loads go straight to LDS (no registers): each instruction moves
@@ -749,10 +773,12 @@ __device__ __forceinline__ void add_bases(const TBT &tb, T (&n)[Q])
 
 // Pulled populations N_a(i, j) of Eq. (adv) with the boundary sources of
 // App. B, read from the post-collision field in HBM and moved to the cell's
-// compute base.  j0 is the first column of the wave's 64.
-template <int Q, typename T, typename S, int CT, bool WIDE, bool BASES = true, typename TBT>
+// compute base.  j0 is the first column of the wave's 64.  XW: each value as
+// loaded (before any base or wall term) also goes to xw[(a - 1) * 64], a = 1..Q-1,
+// the lane's slots of the exchange tile.
+template <int Q, typename T, typename S, int CT, bool WIDE, bool BASES = true, bool XW = false, typename TBT>
 __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const TBT &tb, int i, int j, int j0, int pin,
-                                          T (&n)[Q])
+                                          T (&n)[Q], T *xw = nullptr)
 {
     constexpr int CM = cmax<Q>();
     constexpr double T0d = lattice_T0<Q>();
@@ -797,6 +823,7 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
             for (int a = 0; a < Q; ++a) {
                 const uint32_t soff = (uint32_t)a * sa_b + (uint32_t)(r0 - cx(a)) * sr_b + blk;
                 n[a] = pload<Q, S, T>(rin, vsh[cy(a) + CM], soff, a);
+                if constexpr (XW) if (a > 0) xw[(a - 1) * 64] = n[a];
                 // to this cell's compute base (the rest direction pulls from the cell itself)
                 if constexpr (CT == 0) n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             }
@@ -806,6 +833,7 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
             for (int a = 0; a < Q; ++a) {
                 const uint32_t soff = (uint32_t)((int)(a * sa_b + (r0 - cx(a)) * sr_b) - cy(a) * (int)ES);
                 n[a] = pload<Q, S, T>(rin, jb, soff, a);
+                if constexpr (XW) if (a > 0) xw[(a - 1) * 64] = n[a];
                 // to this cell's compute base (the rest direction pulls from the cell itself)
                 if constexpr (CT == 0) n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             }
@@ -843,6 +871,7 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
             // the unwrapped one would)
             const uint32_t rrel = WIDE ? (uint32_t)((wlo || whi ? ti : r) - (i - CM)) : (uint32_t)r;
             T v = pload<Q, S, T>(wlo ? rwlo : (whi ? rwhi : rw), cb, (uint32_t)beta * sa_b + rrel * sr_b, a);
+            if constexpr (XW) if (a > 0) xw[(a - 1) * 64] = v;
             if constexpr (CT == 0) v += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             if (c2 != 0 && wall != 0) {
                 const int sd = wall - 1;
@@ -1198,6 +1227,54 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             tb.setup(d, geo_lds, ref, wave, j - j0, i, j);
         }
         add_bases<Q, T, CT>(tb, n);
+    } else if constexpr (xch_step<Q, S, CT, MOM>()) {
+        extern __shared__ float xch_lds[];
+        T *xt = (T *)xch_lds;
+        if (tl.y >= n1) return;   // padding tile (the whole workgroup)
+        const int nw = (int)(blockDim.x >> 6), lane = (int)(threadIdx.x & 63);
+        const bool act = i < n1 && j < n2;
+        tb.p = (const T *)d->tab + (size_t)i * TB::STRIDE;
+        tb.s = 1;
+        // partner q + c_a of direction a inside the tile (an active cell of
+        // the workgroup's rows and of this wave's 64 columns)
+        auto inside = [&](int a) {
+            const int pr = wave + cx(a), pl = lane + cy(a);
+            return pr >= 0 && pr < nw && i + cx(a) < n1 && pl >= 0 && pl < 64 && j + cy(a) < n2;
+        };
+        T own[Q];
+        if (act) {
+            // the own cell's stored values that no partner in the tile pulls,
+            // loaded first so that they are in flight with the pulls.  Every
+            // lane issues the load, without a branch, so that the loads
+            // overlap; a lane whose value comes from the tile loads from
+            // offset 2^31, past the end of the resource (2 GiB at most), which
+            // returns zero without touching memory
+            constexpr uint32_t ES = sizeof(S);
+            const uint32_t sa_b = (uint32_t)d->sa * ES, sb_b = (uint32_t)d->sb * ES;
+            const uint32_t jb = (uint32_t)(j >> d->bs) * sb_b + (uint32_t)(j & d->bm) * ES;
+            const __amdgpu_buffer_rsrc_t rown = WIDE ? row_rsrc(d->P[pin], (size_t)d->sr * ES, i, 1)
+                                                     : make_rsrc(d->P[pin], (uint32_t)(d->plane * Q) * ES);
+            const uint32_t rowb = WIDE ? 0u : (uint32_t)i * (uint32_t)d->sr * ES;
+#pragma unroll
+            for (int a = 1; a < Q; ++a)
+                own[a] = pload<Q, S, T>(rown, inside(a) ? 0x80000000u : jb + (uint32_t)a * sa_b + rowb, 0u, a);
+            pull_cell<Q, T, S, CT, WIDE, true, true>(d, tb, i, j, j0, pin, n, xt + wave * (Q - 1) * 64 + lane);
+        }
+        __syncthreads();
+        if (!act) return;
+        // lagged own-cell force sums sum_a A+^i_a N'_a(q, t - 1), in the
+        // stored sums' order; the tile index is clamped into the tile, so
+        // the read stays inside it whichever way the select goes
+        Lo1 = 0;
+        Lo2 = 0;
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            const int pr = min(max(wave + cx(a), 0), nw - 1), pl = min(max(lane + cy(a), 0), 63);
+            const T x = xt[(pr * (Q - 1) + a - 1) * 64 + pl];
+            const T v = (inside(a) ? x : own[a]) - tb(TB::SB(a));
+            Lo1 += tb(TB::A1(a)) * v;
+            Lo2 += tb(TB::A2(a)) * v;
+        }
     } else {
         if (i >= n1 || j >= n2) return;
         if constexpr (CT == 1) {
@@ -1231,7 +1308,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
         mo[3 * nc + c] = (double)o.Ut1;
         mo[4 * nc + c] = (double)o.Ut2;
     } else {
-        store_cell<Q, T, S, CT, true, WIDE>(d, tb, i, j, pin, s, o);
+        store_cell<Q, T, S, CT, !xch_step<Q, S, CT, MOM>(), WIDE>(d, tb, i, j, pin, s, o);
     }
 }
 

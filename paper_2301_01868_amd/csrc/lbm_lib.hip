@@ -157,8 +157,9 @@ static size_t comp_size(int precision) { return precision == LBM_FP64 ? sizeof(d
 static dim3 cell_grid(int n1, int n2) { return dim3((n2 + 127) / 128, n1); }
 
 // Dynamic LDS reserved per workgroup of a step launch to cap the resident
-// waves per CU at `cap` (0: no reservation).  The step kernels use no LDS;
-// the reservation only limits how many workgroups share a CU's 160 KiB.  At
+// waves per CU at `cap` (0: no reservation).  Beyond the staged geometry of
+// per-cell steps and the exchange tile of D2Q9 steps the step kernels use no
+// LDS; the reservation only limits how many workgroups share a CU's 160 KiB.  At
 // most 64 KiB is reserved per workgroup, so caps below three workgroups per
 // CU are not enforced exactly.
 static unsigned occupancy_lds(int cap, int wpb)
@@ -229,6 +230,14 @@ static unsigned step_lds(int ct, int q, int precision, int cap, int wpb)
         const unsigned sg = q == 9 ? (precision == LBM_FP64 ? geo_stage_bytes<9, double>() : geo_stage_bytes<9, float>())
                                    : (precision == LBM_FP64 ? geo_stage_bytes<21, double>() : geo_stage_bytes<21, float>());
         if (sg > b) b = sg;
+    }
+    if (ct == 0 && (q == 9 || q == 0) && precision != LBM_FP16) {
+        // the D2Q9 exchange tile (q = 0: the group's D2Q9 tiles) of FP32 and FP64 storage
+        static_assert(xch_step<9, float, 0, false>() && xch_step<9, double, 0, false>() &&
+                          !xch_step<9, _Float16, 0, false>() && !xch_step<21, float, 0, false>(),
+                      "exchange tiles of D2Q9 FP32 and FP64 steps only");
+        const unsigned xb = precision == LBM_FP64 ? xch_bytes<9, double>(wpb) : xch_bytes<9, float>(wpb);
+        if (xb > b) b = xb;
     }
     return b;
 }
