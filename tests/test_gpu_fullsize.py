@@ -246,6 +246,53 @@ def test_large_single_grid(prec, make, n1, n2, tol1):
     g.close()
 
 
+def _annulus9(n1, n2):
+    return G.circular_couette(9, n1, n2, float(n1), u_inner=0.05, tau=0.8)
+
+
+def _channel9(n1, n2):
+    return G.planar_couette(9, G.faces_uniform(n1), n2=n2, u_wall=0.05, tau=0.8)
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("prec,make,n1,n2,tol1", [(lbm.LBM_FP32, _annulus9, 4096, 16384, 3e-6),
+                                                  (lbm.LBM_FP64, _channel9, 2048, 16384, 1e-13)],
+                         ids=["fp32_q9_annulus_4096x16384", "fp64_q9_channel_2048x16384"])
+def test_large_d2q9_grid_exchange_tile(prec, make, n1, n2, tol1):
+    """D2Q9 grids whose population buffers pass 2 GiB (2.4 GB each): the step
+    that takes the own cell's lagged values from the workgroup's exchange tile
+    addresses them through row-based resources, the own-cell loads of
+    partners outside the tile included.  One step from a sheared state
+    against the oracle on sampled cells; and 1-row workgroups (every partner in
+    another row loaded from HBM) end with the same bits as 4-row ones."""
+    case = make(n1, n2)
+    say("large D2Q9 grid", case.meta["problem"], n1, "x", n2, "prec", prec)
+    s = 8 if prec == lbm.LBM_FP64 else 4
+    pitch = (n2 + 63) // 64 * 64
+    assert 9 * n1 * pitch * s >= 2 ** 31
+    i = (np.arange(n1)[:, None] + 0.5) / n1
+    j = (np.arange(n2)[None, :] + 0.5) / n2
+    u0 = np.zeros((n1, n2, 2))
+    u0[..., 1] = 0.01 * (1.0 + i) * np.sin(2 * np.pi * 7 * j)
+    u0 = u0.reshape(-1, 2)
+    states = []
+    for wpb in (1, 4):
+        g = lbm.Grid(case, precision=prec)
+        assert g.info.row_tables == 1
+        g.set_launch(wpb)
+        g.init(u0)
+        g.step(3)
+        assert g.residual(check=False).bad_cells == 0
+        states.append(g.get_state()[0])
+        if wpb == 4:
+            say("large D2Q9 grid stepped; oracle one-step on sampled cells")
+            e1 = _one_step_sampled(g, case, nsample=3000)
+            say("large D2Q9 grid one-step sampled rel err", e1)
+            assert e1 <= tol1
+        g.close()
+    assert np.array_equal(states[0], states[1])
+
+
 @pytest.mark.timeout(1200)
 def test_wide_periodic_box_in_a_fused_batch():
     """A doubly periodic, wobbled box whose FP32 population buffer passes
