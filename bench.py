@@ -161,8 +161,10 @@ def measure(cases, prec, steps, warmup, wpb=0, stream=None, workload=None, unbat
     batch = lbm.lbm_batch_create([g.h for g in grids]) if len(grids) > 1 else None
     if batch is not None:
         # each group's launch shape timed on the whole group (the per-grid choices above
-        # serve the one-grid-at-a-time comparison); the trials advance every grid alike
-        lbm.lbm_batch_autotune(batch, 20)
+        # serve the one-grid-at-a-time comparison); the trials advance every grid alike.
+        # 64 launches per trial: with 20, two sessions with identical D2Q9 kernels kept
+        # different shapes (169 against 178 us per launch)
+        lbm.lbm_batch_autotune(batch, 64)
 
     def run(n):
         if batch is not None:

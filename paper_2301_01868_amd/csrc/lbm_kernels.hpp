@@ -205,6 +205,49 @@ __host__ __device__ constexpr double plane_scale(int a)
     if constexpr (sizeof(S) == 2) return weight<Q>(a);
     else return 1.0;
 }
+// The FP16 plane scales held in vector registers.  A decode (T)h * w + b is
+// one v_fma_mix_f32, and an instruction of that encoding reads at most one
+// scalar register; with both w (a constant) and b (a per-row base term) scalar,
+// every decode needed a v_mov first.  A function that decodes many values
+// makes one of these at its start (identical moves merge, one register per
+// distinct weight).  For FP32 and FP64 storage, and where the base terms are
+// per-lane values already (VREG = false: per-cell tables, stored or rebuilt),
+// it holds nothing and the weights stay constants.
+template <int Q, typename S, typename T, bool VREG = true>
+struct PScale {
+    static constexpr bool V = VREG && sizeof(S) == 2;
+    T w[V ? Q : 1];
+    __device__ __forceinline__ PScale()
+    {
+        if constexpr (V) {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) __asm__("v_mov_b32 %0, %1" : "=v"(w[a]) : "s"((T)plane_scale<Q, S>(a)));
+        }
+    }
+    __device__ __forceinline__ T operator()(int a) const
+    {
+        if constexpr (V) return w[a];
+        else return (T)plane_scale<Q, S>(a);
+    }
+};
+
+template <int Q, typename S, typename T, bool VREG>
+__device__ inline T pload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, int a,
+                          const PScale<Q, S, T, VREG> &ps)
+{
+    if constexpr (sizeof(S) == 2) {
+        const _Float16 h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LD_AUX));
+        return (T)h * ps(a);
+    } else {
+        return bload<S, T>(r, voff, soff);
+    }
+}
+template <int Q, typename S, typename T, bool VREG>
+__device__ inline T pdec(S v, int a, const PScale<Q, S, T, VREG> &ps)
+{
+    if constexpr (sizeof(S) == 2) return (T)v * ps(a);
+    else return (T)v;
+}
 template <int Q, typename S, typename T>
 __device__ inline T pload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, int a)
 {
@@ -279,8 +322,8 @@ struct TabView {
 // once from FP64, and takes every difference and term in FP32: a difference
 // over one cell then carries the rounding of deviations of at most about 35
 // cells' variation, a few 1e-6 of itself, and the step needs no FP64
-// arithmetic per direction (which runs at half the FP32 rate and took most
-// of the kernel's vector ALU time).
+// arithmetic per direction (FP64 values take two registers and two LDS words
+// each, which held FP32 compute to fewer waves).
 // ---------------------------------------------------------------------------
 enum { GE_G1X = 0, GE_G1Y, GE_G2X, GE_G2Y, GE_J, GE_H11, GE_H12, GE_H22, GE_NF };
 
@@ -796,6 +839,7 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
     // byte offset of the wave's own cells inside a row
     const uint32_t jb = (uint32_t)(j >> bs) * sb_b + (uint32_t)(j & bm) * ES;
 
+    const PScale<Q, S, T, CT == 0> ps;
     const bool interior = (i >= CM && i < n1 - CM);
     const bool nowrap = (j0 >= CM) && (j0 + 63 + CM < n2);
     if (interior && nowrap) {
@@ -822,7 +866,7 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
                 const uint32_t soff = (uint32_t)a * sa_b + (uint32_t)(r0 - cx(a)) * sr_b + blk;
-                n[a] = pload<Q, S, T>(rin, vsh[cy(a) + CM], soff, a);
+                n[a] = pload<Q, S, T>(rin, vsh[cy(a) + CM], soff, a, ps);
                 if constexpr (XW) if (a > 0) xw[(a - 1) * 64] = n[a];
                 // to this cell's compute base (the rest direction pulls from the cell itself)
                 if constexpr (CT == 0) n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
@@ -832,7 +876,7 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
                 const uint32_t soff = (uint32_t)((int)(a * sa_b + (r0 - cx(a)) * sr_b) - cy(a) * (int)ES);
-                n[a] = pload<Q, S, T>(rin, jb, soff, a);
+                n[a] = pload<Q, S, T>(rin, jb, soff, a, ps);
                 if constexpr (XW) if (a > 0) xw[(a - 1) * 64] = n[a];
                 // to this cell's compute base (the rest direction pulls from the cell itself)
                 if constexpr (CT == 0) n[a] += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
@@ -870,7 +914,7 @@ __device__ __forceinline__ void pull_cell(const InstDesc *__restrict__ d, const 
             // row inside its resource (a wrapped row sits in its window where
             // the unwrapped one would)
             const uint32_t rrel = WIDE ? (uint32_t)((wlo || whi ? ti : r) - (i - CM)) : (uint32_t)r;
-            T v = pload<Q, S, T>(wlo ? rwlo : (whi ? rwhi : rw), cb, (uint32_t)beta * sa_b + rrel * sr_b, a);
+            T v = pload<Q, S, T>(wlo ? rwlo : (whi ? rwhi : rw), cb, (uint32_t)beta * sa_b + rrel * sr_b, a, ps);
             if constexpr (XW) if (a > 0) xw[(a - 1) * 64] = v;
             if constexpr (CT == 0) v += (a > 0) ? tb(TB::DB(a)) : -tb(TB::SB(0));
             if (c2 != 0 && wall != 0) {
@@ -1081,6 +1125,7 @@ __device__ __forceinline__ void store_cell(const InstDesc *__restrict__ d, const
     const __amdgpu_buffer_rsrc_t rout = WIDE ? row_rsrc(d->P[pin ^ 1], (size_t)d->sr * ES, i, 1)
                                              : make_rsrc(d->P[pin ^ 1], (uint32_t)(d->plane * Q) * ES);
     const uint32_t rowb = WIDE ? 0u : (uint32_t)i * (uint32_t)d->sr * ES;
+    const PScale<Q, S, T, CT == 0> ps;
     T Lx1 = 0, Lx2 = 0;
     auto store_all = [&](auto with_sb) {
 #pragma unroll
@@ -1089,7 +1134,7 @@ __device__ __forceinline__ void store_cell(const InstDesc *__restrict__ d, const
             const T st = s[a] + sb;                                             // storage base
             pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + rowb, a, st);
             if constexpr (LAGW) {
-                const T v = pdec<Q, S, T>(penc<Q, S, T>(st, a), a) - sb;     // as stored, compute base
+                const T v = pdec<Q, S, T>(penc<Q, S, T>(st, a), a, ps) - sb;     // as stored, compute base
                 if (a > 0) {
                     Lx1 += tb(TB::A1(a)) * v;
                     Lx2 += tb(TB::A2(a)) * v;
@@ -1109,7 +1154,7 @@ __device__ __forceinline__ void store_cell(const InstDesc *__restrict__ d, const
             const T st = s[a] + tb(TB::SB(a));                                  // storage base
             pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + rowb, a, st);
             if constexpr (LAGW) {
-                const T v = pdec<Q, S, T>(penc<Q, S, T>(st, a), a) - tb(TB::SB(a));  // as stored, compute base
+                const T v = pdec<Q, S, T>(penc<Q, S, T>(st, a), a, ps) - tb(TB::SB(a));  // as stored, compute base
                 if (a > 0) {
                     Lx1 += tb(TB::A1(a)) * v;
                     Lx2 += tb(TB::A2(a)) * v;
@@ -1155,11 +1200,12 @@ __device__ __forceinline__ void own_lag_global(const InstDesc *__restrict__ d, c
     const __amdgpu_buffer_rsrc_t rin = WIDE ? row_rsrc(d->P[pin], (size_t)d->sr * ES, i, 1)
                                             : make_rsrc(d->P[pin], (uint32_t)(d->plane * Q) * ES);
     const uint32_t rowb = WIDE ? 0u : (uint32_t)i * (uint32_t)d->sr * ES;
+    const PScale<Q, S, T> ps;
     Lo1 = 0;
     Lo2 = 0;
 #pragma unroll
     for (int a = 1; a < Q; ++a) {
-        const T v = pload<Q, S, T>(rin, jb, (uint32_t)a * sa_b + rowb, a) - tb(TB::SB(a));
+        const T v = pload<Q, S, T>(rin, jb, (uint32_t)a * sa_b + rowb, a, ps) - tb(TB::SB(a));
         Lo1 += tb(TB::A1(a)) * v;
         Lo2 += tb(TB::A2(a)) * v;
     }
@@ -1255,9 +1301,10 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
             const __amdgpu_buffer_rsrc_t rown = WIDE ? row_rsrc(d->P[pin], (size_t)d->sr * ES, i, 1)
                                                      : make_rsrc(d->P[pin], (uint32_t)(d->plane * Q) * ES);
             const uint32_t rowb = WIDE ? 0u : (uint32_t)i * (uint32_t)d->sr * ES;
+            const PScale<Q, S, T> ps;
 #pragma unroll
             for (int a = 1; a < Q; ++a)
-                own[a] = pload<Q, S, T>(rown, inside(a) ? 0x80000000u : jb + (uint32_t)a * sa_b + rowb, 0u, a);
+                own[a] = pload<Q, S, T>(rown, inside(a) ? 0x80000000u : jb + (uint32_t)a * sa_b + rowb, 0u, a, ps);
             pull_cell<Q, T, S, CT, WIDE, true, true>(d, tb, i, j, j0, pin, n, xt + wave * (Q - 1) * 64 + lane);
         }
         __syncthreads();
