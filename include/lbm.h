@@ -368,10 +368,11 @@ int lbm_batch_step_group(lbm_batch *b, int32_t group, int64_t n);
 /* Autotuner for a batch: for each group, times `steps` launches (rounded up
  * to even, after 2 untimed ones) of the group's own step kernel over all of
  * its tiles for each tile shape (1, 2 or 4 rows per workgroup) and each
- * occupancy cap (none, 24, 20 or 16 waves per CU), and keeps the fastest pair
+ * occupancy cap (none, 24, 20 or 16 waves per CU), in two sweeps over these
+ * 12 configurations, and keeps the pair with the fastest of its two times
  * for that group (until then a group launches with the choice of its first
  * grid).  The trials step the batch's own state: every grid advances by the
- * same even number of steps, 12 (steps + 2), exactly as lbm_batch_step would
+ * same even number of steps, 24 (steps + 2), exactly as lbm_batch_step would
  * have advanced it, since no result depends on the launch shape.  Step
  * counters advance accordingly.  Synchronises; LBM_EINVAL for a null batch,
  * LBM_ENOMEM / LBM_EDEVICE if a trial's tile table or launch fails (the
@@ -396,7 +397,8 @@ int lbm_set_occupancy(lbm_grid *g, int32_t waves_per_cu);
 
 /* Autotuner: times `steps` step launches for each tile shape (1, 2 or 4
  * waves, i.e. rows, per workgroup) and each occupancy cap (none, 24, 20 or
- * 16 waves per CU), keeps the fastest pair and caches it for the process per
+ * 16 waves per CU), in two sweeps, keeps the pair with the fastest of its two
+ * times and caches it for the process per
  * (q, precision, table kind, n1, n2).  The timing steps run on the grid's own
  * buffers, so call it between create and init (the grid needs lbm_init
  * afterwards).  Returns the chosen waves per workgroup (> 0; the cap is in

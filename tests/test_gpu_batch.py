@@ -60,16 +60,16 @@ def test_batch_autotune_advances_like_steps(fuse):
     plain[1].step(3)
     bt = lbm.lbm_batch_create_ex([g.h for g in tuned], fuse)
     s0 = [g.info.step for g in tuned]
-    lbm.lbm_batch_autotune(bt, 3)                     # rounded up to 4: 12 x 6 = 72 steps
+    lbm.lbm_batch_autotune(bt, 3)                     # rounded up to 4: 2 sweeps x 12 x 6 = 144 steps
     adv = [g.info.step - s for g, s in zip(tuned, s0)]
     say("autotune advanced", adv, "shapes", [lbm.lbm_batch_group_launch(bt, k) for k in range(len(lbm.lbm_batch_groups(bt)))])
-    assert adv == [72] * len(cases)
+    assert adv == [144] * len(cases)
     for k in range(len(lbm.lbm_batch_groups(bt))):
         w, c = lbm.lbm_batch_group_launch(bt, k)
         assert w in (1, 2, 4) and c in (0, 16, 20, 24)
     lbm.lbm_batch_step(bt, 41)
     bp = lbm.lbm_batch_create_ex([g.h for g in plain], fuse)
-    lbm.lbm_batch_step(bp, 72 + 41)
+    lbm.lbm_batch_step(bp, 144 + 41)
     lbm.lbm_batch_destroy(bt)
     lbm.lbm_batch_destroy(bp)
     for gt, gp, c in zip(tuned, plain, cases):
@@ -99,15 +99,15 @@ def test_batch_autotune_per_cell_and_iterated_groups():
     bt = lbm.lbm_batch_create([g.h for g in tuned])
     ngroups = len(lbm.lbm_batch_groups(bt))
     assert ngroups == 3
-    lbm.lbm_batch_autotune(bt, 2)                     # 12 x 4 = 48 steps
+    lbm.lbm_batch_autotune(bt, 2)                     # 2 sweeps x 12 x 4 = 96 steps
     say("per-cell / iterated autotune shapes", [lbm.lbm_batch_group_launch(bt, k) for k in range(ngroups)])
     lbm.lbm_batch_step(bt, 21)
     bp = lbm.lbm_batch_create([g.h for g in plain])
-    lbm.lbm_batch_step(bp, 48 + 21)
+    lbm.lbm_batch_step(bp, 96 + 21)
     lbm.lbm_batch_destroy(bt)
     lbm.lbm_batch_destroy(bp)
     for gt, gp in zip(tuned, plain):
-        assert gt.info.step == gp.info.step == 69
+        assert gt.info.step == gp.info.step == 117
         Pt, st = gt.get_state()
         Pp, sp = gp.get_state()
         assert np.array_equal(Pt, Pp)
