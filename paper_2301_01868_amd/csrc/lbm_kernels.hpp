@@ -421,6 +421,13 @@ __device__ __forceinline__ const double *stage_geometry(const InstDesc *__restri
 // tl.z), into the LDS tile; ref[f] receives those reference values.  All
 // loads of a pass are issued before its stores.  Returns the tile; the
 // caller waits for the other waves (barrier) before reading it.
+// J and H are read only at the pulled sources (the base differences).
+// Beyond a wall the pulled source is the mirror cell (App. B), so the tile
+// rows past a wall hold the mirror row's J and H there, with H12 negated at a
+// moving wall (the specular direction flips c^1, hence the sign of the c^1 c^2
+// H12 term of the source's rest state): every base difference then reads the
+// row of q - c_a, whatever the row of q.  The tangents keep the ghost rows of
+// the extended geometry (the rebuilt Christoffel sums difference them).
 template <int Q>
 __device__ __forceinline__ const float *stage_geometry_f(const InstDesc *__restrict__ d, const int4 tl, int wave,
                                                          double (&ref)[GE_NF])
@@ -441,13 +448,34 @@ __device__ __forceinline__ const float *stage_geometry_f(const InstDesc *__restr
     // again), U rows per pass with every load issued before the stores
     constexpr int U = 4;
     const int nrows = GE_NF * TR;
+    const int n1 = d->n1;
+    const bool walls = !d->periodic1;
+    const bool flip_lo = d->bc_lo != BC_NOSLIP, flip_hi = d->bc_hi != BC_NOSLIP;
+    // extended geometry row of tile row rr of field f, and whether its value is negated
+    auto src_row = [&](int f, int rr, bool &neg) {
+        int er = min(tl.y + rr, ger - 1);
+        neg = false;
+        if (walls && f >= GE_J) {
+            const int ti = er - CM;   // cell row
+            if (ti < 0) {
+                er = -1 - ti + CM;
+                neg = f == GE_H12 && flip_lo;
+            } else if (ti >= n1) {
+                er = 2 * n1 - 1 - ti + CM;
+                neg = f == GE_H12 && flip_hi;
+            }
+            er = min(max(er, 0), ger - 1);   // rows no cell reads (narrow grids) stay in range
+        }
+        return er;
+    };
     for (int t0 = wave; t0 < nrows; t0 += U * nw) {
         double v[U][2];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u * nw;
             const int f = t / TR, rr = t - f * TR;
-            const int er = min(tl.y + rr, ger - 1);
+            bool neg;
+            const int er = src_row(f, rr, neg);
             const double *src = ge + f * gfs + (size_t)er * gw;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -460,14 +488,18 @@ __device__ __forceinline__ const float *stage_geometry_f(const InstDesc *__restr
             const int t = t0 + u * nw;
             if (t < nrows) {
                 const int f = t / TR, rr = t - f * TR;
+                bool neg;
+                (void)src_row(f, rr, neg);
                 double r = ref[0];
 #pragma unroll
                 for (int g = 1; g < GE_NF; ++g)
                     if (f == g) r = ref[g];
+                // +-v - r in one rounding (the sign is exact), the same bits as v - r
+                const double sg = neg ? -1.0 : 1.0;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int cc = lane + 64 * h;
-                    if (cc < TC) geo_ldsf[f * FS + rr * TC + cc] = (float)(v[u][h] - r);
+                    if (cc < TC) geo_ldsf[f * FS + rr * TC + cc] = (float)__builtin_fma(sg, v[u][h], -r);
                 }
             }
         }
@@ -485,9 +517,8 @@ struct GeoTabF {
     static constexpr int TC = geo_tile_cols<Q>(), FS = geo_tile_field<Q>();
     const float *L;    // staged deviations
     int o;             // own cell in a staged field
-    int i, n1, per1, bclo, bchi;
     float eJ, e11, e12, e22, e1x, e1y, e2x, e2y;   // own deviations
-    float rho0f, r12;  // rho0, reference H12 (for mirrored sources)
+    float rho0f;
     T u1x, u1y, u2x, u2y, G11, G12, G22, mb, c1s, c2s, kpi;
 
     __device__ __forceinline__ float ld(int f, int dr, int dc) const { return L[o + (f * FS + dr * TC + dc)]; }
@@ -528,11 +559,6 @@ struct GeoTabF {
     {
         L = lds;
         o = (wave + CM) * TC + lane + CM;
-        i = row;
-        n1 = d->n1;
-        per1 = d->periodic1;
-        bclo = d->bc_lo;
-        bchi = d->bc_hi;
         const double rho0 = d->rho0;
         rho0f = (float)rho0;
         kpi = (T)d->kpi;
@@ -544,7 +570,6 @@ struct GeoTabF {
         e11 = ld(GE_H11, 0, 0);
         e12 = ld(GE_H12, 0, 0);
         e22 = ld(GE_H22, 0, 0);
-        r12 = (float)ref[GE_H12];
         // the cell's own values, once per cell in FP64
         const double g1x = ref[GE_G1X] + e1x, g1y = ref[GE_G1Y] + e1y;
         const double g2x = ref[GE_G2X] + e2x, g2y = ref[GE_G2Y] + e2y;
@@ -588,23 +613,14 @@ struct GeoTabF {
     // flipped at a moving wall flips the sign of the source's c1 c2 H12 term)
     __device__ __forceinline__ T dbase(int a) const
     {
-        const int ti = i - cx(a);
-        const bool lo = ti < 0, hi = ti >= n1;
-        int dr = -cx(a);
-        bool flip = false;
-        if (!per1 && (lo || hi)) {
-            // mirror image across the wall: source row r, direction reversed
-            // (no-slip) or with its q1 component flipped (moving)
-            const int r = lo ? -1 - ti : 2 * n1 - 1 - ti;
-            dr = r - i;
-            flip = (lo ? bclo : bchi) != BC_NOSLIP;
-        }
-        const int dc = -cy(a);
+        // the source q - c_a: past a wall, the staged tile holds the mirror
+        // cell's J and H there (with H12 negated at a moving wall)
+        const int dr = -cx(a), dc = -cy(a);
         const T c1 = (T)cx(a), c2 = (T)cy(a);
         const T dJ = ld(GE_J, dr, dc) - eJ;
         const T d11 = ld(GE_H11, dr, dc) - e11;
         const T d22 = ld(GE_H22, dr, dc) - e22;
-        const T d12 = flip ? -(ld(GE_H12, dr, dc) + e12) - (T)2 * r12 : ld(GE_H12, dr, dc) - e12;
+        const T d12 = ld(GE_H12, dr, dc) - e12;
         return rho0f * (T)weight<Q>(a) *
                ((T)(2.0 - (cx(a) * cx(a) + cy(a) * cy(a)) / (2.0 * T0)) * dJ +
                 (c1 * c1 * d11 + (T)2 * c1 * c2 * d12 + c2 * c2 * d22 - (T)T0 * (d11 + d22)) * (T)(1.0 / (2.0 * T0)));
@@ -1363,7 +1379,7 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
 // table holds (instance, first row, first column, lattice).  WIDE instances
 // serve population buffers of 2 GiB and more.
 template <int Q, typename T, typename S, int CT, bool MOM, bool ITER, bool WIDE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CT == 2 && sizeof(T) == 4 && Q == 21 ? 4 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CT == 2 && sizeof(T) == 4 && Q == 21 ? (ITER ? 4 : 5) : 1)))
 void k_step(const InstDesc *__restrict__ insts, const int4 *__restrict__ tiles, int par)
 {
     step_tile<Q, T, S, CT, MOM, ITER, WIDE>(insts, tiles[blockIdx.x], par);
