@@ -57,12 +57,16 @@ __device__ __forceinline__ void sfor(F &&f)
 // momentum-flux correction is then a per-row moment table contracted with K:
 //   J dPi^ij = kpi m sum_k K_k T^ij_k,  T^ij_k = sum_a w_a c^i_a S^j_a P_k(c_a),
 // S^j_a = A+^j_a + A+^j_{-a}, the same sum over directions in another order.
+// The correction dN_a of Eq. (deltaN) contracts dPi with the symmetric c_a c_a,
+// so only the symmetric parts are needed: for x <= y the table holds
+// U^xy_k = T^xy_k + T^yx_k (x < y) or T^xx_k, and
+//   sum_ij c^i c^j J dPi^ij = kpi m sum_{x <= y} c^x c^y sum_k K_k U^xy_k.
 constexpr int NK = 20;
 // per-row table: g^11, g^12, g^13, g^22, g^23, g^33; A+^i_a at 6 + 3 a + i;
-// T^ij_k at TT + (3 i + j) NK + k
+// U^xy_k at TT + sym2(x, y) NK + k
 constexpr int TG = 6 + 3 * Q;
 constexpr int TT = TG;
-constexpr int TW = TG + 9 * NK;
+constexpr int TW = TG + 6 * NK;
 // per-cell geometry output: J, the six g^ij, A+ (3 Q)
 constexpr int GW = 1 + TG;
 
@@ -245,7 +249,8 @@ __device__ __forceinline__ double phi_poly(const double K[NK])
 
 // MOM = true writes the moments the next step would see instead of colliding
 template <bool MOM>
-__global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int par)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MOM ? 1 : 3)))
+void k_step3(const Desc3 *__restrict__ dp, int par)
 {
     const cptr3<Desc3> d = (cptr3<Desc3>)dp;
     Cell3 c;
@@ -350,59 +355,67 @@ __global__ __launch_bounds__(64) void k_step3(const Desc3 *__restrict__ dp, int 
         const double G[6] = {tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]};   // 11 12 13 22 23 33
         double K[NK];
         eq_coeffs(G, U, Ut, K);
-        // ---- the momentum-flux correction through the per-row moment table ----
-        double dPi[3][3];
+        // ---- the momentum-flux correction through the per-row moment table
+        // (its symmetric parts: Q^xy = J dPi^xy + J dPi^yx for x < y, J dPi^xx) ----
+        double Qs[6];
+        sfor<0, 6>([&](auto XY) {
+            constexpr int xy = decltype(XY)::value;
+            double s = 0.0;
 #pragma unroll
-        for (int x = 0; x < 3; ++x)
-#pragma unroll
-            for (int y = 0; y < 3; ++y) {
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < NK; ++k) s += tb[TT + (3 * x + y) * NK + k] * K[k];
-                dPi[x][y] = d->kpi * m * s;
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        const double trPi = dPi[0][0] + dPi[1][1] + dPi[2][2];
+            for (int k = 0; k < NK; ++k) s += tb[TT + xy * NK + k] * K[k];
+            Qs[xy] = d->kpi * m * s;
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        const double trPi = Qs[sym2(0, 0)] + Qs[sym2(1, 1)] + Qs[sym2(2, 2)];
 
         // ---- correction, BGK, store; the next step's lagged force sums ----
+        // N'_a = (1 - omega) N_a + omega m phi_a + dN_a.  Both omega m phi_a
+        // and dN_a are polynomials in c_a: dN's constant part (-tr dPi / T0),
+        // linear part (c.JF / T0) and quadratic part (c c : dPi / T0^2) fold
+        // into the equilibrium's coefficients, K' = omega m K + those, so that
+        //   N'_a = (1 - omega) N_a + w_a sum_k P_k(c_a) K'_k
+        // (this frees the correction's registers before the store: the kernel
+        // fits three waves per SIMD)
+        {
+            const double om = d->omega * m;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) K[k] *= om;
+            K[0] -= trPi * (1.0 / T0);
+#pragma unroll
+            for (int x = 0; x < 3; ++x) K[1 + x] += JF[x] * (1.0 / T0);
+#pragma unroll
+            for (int xy = 0; xy < 6; ++xy) K[4 + xy] += Qs[xy] * (1.0 / (T0 * T0));
+        }
+        const double omw = 1.0 - d->omega;
         double *__restrict__ Pout = d->P[pin ^ 1];
         double Ln[3] = {0.0, 0.0, 0.0};
-        // the rest direction, then the pairs (a, -a) = (2p - 1, 2p): the even and
-        // odd parts of the equilibrium polynomial, c.JF and c c : dPi are formed
-        // once per pair (the odd ones flip sign for -a)
-        auto store = [&](auto Aic, double mp, double dN) {
+        // the Christoffel sums are read again from the scalar cache here: an
+        // opaque copy of the row pointer keeps the compiler from holding the
+        // 117 values loaded for the force in scalar registers across the step
+        cptr3<double> tbs = tb;
+        __asm__ volatile("" : "+s"(tbs));
+        auto store = [&](auto Aic, double wphi) {
             constexpr int a = decltype(Aic)::value;
-            const double np = n[a] - (n[a] - mp) * d->omega + dN;
+            const double np = omw * n[a] + wphi;
             Pout[pidx3(d->n2, d->pitch, c.i, c.j, a, c.k)] = np;
             if constexpr (a > 0) {
-                Ln[0] += tb[6 + 3 * a + 0] * np;
-                Ln[1] += tb[6 + 3 * a + 1] * np;
-                Ln[2] += tb[6 + 3 * a + 2] * np;
+                Ln[0] += tbs[6 + 3 * a + 0] * np;
+                Ln[1] += tbs[6 + 3 * a + 1] * np;
+                Ln[2] += tbs[6 + 3 * a + 2] * np;
             }
         };
-        store(std::integral_constant<int, 0>{}, m * phi_poly<0>(K), -(weight(0) / T0) * trPi);
+        // the rest direction, then the pairs (a, -a) = (2p - 1, 2p): the even
+        // and odd parts of the polynomial are formed once per pair (the odd
+        // one flips sign for -a)
+        store(std::integral_constant<int, 0>{}, phi_poly<0>(K));
         __builtin_amdgcn_sched_barrier(0);
         sfor<1, (Q + 1) / 2>([&](auto Pc) {
             constexpr int a = 2 * decltype(Pc)::value - 1, b = a + 1;
             static_assert(opp(a) == b, "pairs (2p - 1, 2p)");
-            double t1 = 0.0, t2 = 0.0;
-            sfor<0, 3>([&](auto X) {
-                constexpr int x = decltype(X)::value;
-                if constexpr (cvec(a, x) != 0) {
-                    t1 += cvec(a, x) * JF[x];
-                    sfor<0, 3>([&](auto Y) {
-                        constexpr int y = decltype(Y)::value;
-                        if constexpr (cvec(a, y) != 0) t2 += (double)(cvec(a, x) * cvec(a, y)) * dPi[x][y];
-                    });
-                }
-            });
             double E, O;
             phi_parts<a>(K, E, O);
-            const double mw = m * weight(a);
-            // the constants fold at compile time: no division per direction
-            const double dNe = (weight(a) / (T0 * T0)) * t2 - (weight(a) / T0) * trPi, dNo = (weight(a) / T0) * t1;
-            store(std::integral_constant<int, a>{}, mw * (E + O), dNe + dNo);
-            store(std::integral_constant<int, b>{}, mw * (E - O), dNe - dNo);
+            store(std::integral_constant<int, a>{}, weight(a) * (E + O));
+            store(std::integral_constant<int, b>{}, weight(a) * (E - O));
             // one pair at a time: without this boundary the scheduler starts
             // every direction's arithmetic at once and runs out of registers
             __builtin_amdgcn_sched_barrier(0);
@@ -527,14 +540,20 @@ __global__ void k_rowtab3(const double *geo, int n1, int n2, int n3, double *tab
     const double *r = geo + (long long)i * n2 * n3 * GW;
     for (int f = (int)threadIdx.x; f < TG; f += (int)blockDim.x) tab[(size_t)i * TW + f] = r[1 + f];
     if (threadIdx.x == 0) Jrow[i] = r[0];
-    for (int e = (int)threadIdx.x; e < 9 * NK; e += (int)blockDim.x) {
-        const int x = e / (3 * NK), y = (e / NK) % 3, k = e % NK;
+    for (int e = (int)threadIdx.x; e < 6 * NK; e += (int)blockDim.x) {
+        const int xy = e / NK, k = e % NK;
+        constexpr int px[6] = {0, 0, 0, 1, 1, 2}, py[6] = {0, 1, 2, 1, 2, 2};   // the sym2 order
+        const int x = px[xy], y = py[xy];
         double s = 0.0;
         for (int a = 1; a < Q; ++a) {
             const int p = mono(k, cvec(a, 0), cvec(a, 1), cvec(a, 2));
-            if (cvec(a, x) == 0 || p == 0) continue;
-            const double S = r[1 + 6 + 3 * a + y] + r[1 + 6 + 3 * opp(a) + y];
-            s += weight(a) * cvec(a, x) * S * p;
+            if (p == 0) continue;
+            const double Sx = r[1 + 6 + 3 * a + x] + r[1 + 6 + 3 * opp(a) + x];
+            const double Sy = r[1 + 6 + 3 * a + y] + r[1 + 6 + 3 * opp(a) + y];
+            // w_a c^x S^y P_k (+ w_a c^y S^x P_k off the diagonal)
+            double t = cvec(a, x) * Sy;
+            if (x != y) t += cvec(a, y) * Sx;
+            s += weight(a) * t * p;
         }
         tab[(size_t)i * TW + TT + e] = s;
     }
