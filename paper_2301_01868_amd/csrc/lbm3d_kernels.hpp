@@ -351,6 +351,21 @@ void k_step3(const Desc3 *__restrict__ dp, int par)
         }
         return;
     } else {
+        // side state of the moving walls: m, Ut^2, Ut^3 of the rows a wall
+        // pulls from (for the next step; written here so that none of it
+        // stays live through the store)
+        double *__restrict__ so = d->side[pin ^ 1];
+        if (d->bc_lo == BC_MOVING && c.i < CMAX) {
+            so[sidx3(d->n2, d->pitch, 0, 0, c.i, c.j, c.k)] = m;
+            so[sidx3(d->n2, d->pitch, 0, 1, c.i, c.j, c.k)] = Ut[1];
+            so[sidx3(d->n2, d->pitch, 0, 2, c.i, c.j, c.k)] = Ut[2];
+        }
+        if (d->bc_hi == BC_MOVING && c.i >= d->n1 - CMAX) {
+            const int row = d->n1 - 1 - c.i;
+            so[sidx3(d->n2, d->pitch, 1, 0, row, c.j, c.k)] = m;
+            so[sidx3(d->n2, d->pitch, 1, 1, row, c.j, c.k)] = Ut[1];
+            so[sidx3(d->n2, d->pitch, 1, 2, row, c.j, c.k)] = Ut[2];
+        }
         // ---- equilibrium coefficients of the cell ----
         const double G[6] = {tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]};   // 11 12 13 22 23 33
         double K[NK];
@@ -423,19 +438,6 @@ void k_step3(const Desc3 *__restrict__ dp, int par)
         d->lag[pin ^ 1][lrow] = Ln[0];
         d->lag[pin ^ 1][lpl + lrow] = Ln[1];
         d->lag[pin ^ 1][2 * lpl + lrow] = Ln[2];
-        // side state of the moving walls: m, Ut^2, Ut^3 of the rows a wall pulls from
-        double *__restrict__ so = d->side[pin ^ 1];
-        if (d->bc_lo == BC_MOVING && c.i < CMAX) {
-            so[sidx3(d->n2, d->pitch, 0, 0, c.i, c.j, c.k)] = m;
-            so[sidx3(d->n2, d->pitch, 0, 1, c.i, c.j, c.k)] = Ut[1];
-            so[sidx3(d->n2, d->pitch, 0, 2, c.i, c.j, c.k)] = Ut[2];
-        }
-        if (d->bc_hi == BC_MOVING && c.i >= d->n1 - CMAX) {
-            const int row = d->n1 - 1 - c.i;
-            so[sidx3(d->n2, d->pitch, 1, 0, row, c.j, c.k)] = m;
-            so[sidx3(d->n2, d->pitch, 1, 1, row, c.j, c.k)] = Ut[1];
-            so[sidx3(d->n2, d->pitch, 1, 2, row, c.j, c.k)] = Ut[2];
-        }
     }
 }
 
