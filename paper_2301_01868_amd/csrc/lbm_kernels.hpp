@@ -357,9 +357,11 @@ __host__ __device__ constexpr unsigned geo_stage_bytes()
 
 // Own-cell values by exchange.  The lagged force of Eq. (compo-constr) needs
 // the own cell's N'_a(q, t-1), which in this step is the value the neighbour
-// q + c_a pulls.  Steps of per-row-table D2Q9 grids take it from there: every
-// lane writes its pulled values, as loaded, to an LDS tile [wave][a - 1][lane]
-// of the workgroup's rows, and after a barrier each cell reads those of its
+// q + c_a pulls.  Steps of D2Q9 grids with per-row tables and FP32 or FP64
+// storage take it from there (FP16 keeps the stored sums: its step is bound
+// by the vector ALU, which the tile's work would add to).  Every lane writes
+// its pulled values, as loaded, to an LDS tile [wave][a - 1][lane] of the
+// workgroup's rows, and after a barrier each cell reads those of its
 // partners inside the tile; the rest (partners in another workgroup's rows or
 // columns, or outside the grid) are loaded from the own cell in HBM.  Either
 // way the value is the stored one, bit for bit, and the sum is formed in the
