@@ -72,3 +72,16 @@ def test_d2q9_exchange_in_batches(fuse):
         for gb, c in zip(batched, cases):
             ga = _run(c, prec, 4, steps=steps)
             assert np.array_equal(ga.get_state()[0], gb.get_state()[0])
+
+
+@pytest.mark.parametrize("prec,pname", PRECS[:2], ids=[p[1] for p in PRECS[:2]])
+def test_d2q9_iterated_force_independent_of_tile(prec, pname):
+    """Fixed-point force passes (iterations > 0) start from the same exchanged
+    own-cell values: the states are the same bits for every tile shape."""
+    name, case = CASES[3]
+    states = []
+    for wpb in (1, 2, 4):
+        g = _run(case, prec, wpb, iterations=2)
+        states.append(g.get_state()[0])
+    say(name, pname, "iterations 2, max diff", float(np.abs(states[2] - states[0]).max()))
+    assert np.array_equal(states[0], states[1]) and np.array_equal(states[0], states[2])
