@@ -34,6 +34,10 @@ def _cases():
     yield "channel_q21_ragged", G.planar_couette(21, G.faces_linear(14, 0.35), n2=70, u_wall=0.04, moving="lo",
                                                   tau=0.7).replace(accel=(0.0, 2e-6))
     yield "couette_q9", G.workload_planar_couette_q9()
+    # a channel of 3 rows between a resting and a moving wall: every D2Q21
+    # source 3 rows out is the mirror of a row on the far side of the channel,
+    # so the staged tile rows past both walls hold mirror rows
+    yield "narrow_q21_moving", G.planar_couette(21, G.faces_uniform(3), n2=70, u_wall=0.03, tau=0.9)
 
 
 CASES = list(_cases())
