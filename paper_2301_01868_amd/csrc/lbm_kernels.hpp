@@ -630,6 +630,47 @@ struct GeoTabF {
     // compute base minus storage base: both the local rest state
     __device__ __forceinline__ T sbdiff(int) const { return (T)0; }
 
+    // Sums over directions of the rebuilt terms, formed on the vectors and
+    // projected once: every A+^i_a is g^i . D_a with D_a = e_a(q + c_a) - e_a(q),
+    // so sum_a A+^i_a x_a = g^i . sum_a D_a x_a; accA adds D_a x_a to V, proj
+    // adds g^i . V to L^i
+    __device__ __forceinline__ void accA(int a, T x, T &V1, T &V2) const
+    {
+        T dx, dy;
+        dA(a, dx, dy);
+        V1 += dx * x;
+        V2 += dy * x;
+    }
+    __device__ __forceinline__ void proj(T V1, T V2, T &L1, T &L2) const
+    {
+        L1 += V1 * u1x + V2 * u1y;
+        L2 += V1 * u2x + V2 * u2y;
+    }
+    // the momentum-flux sums P^ij = sum_p X^ij_p x_p likewise: with S_p =
+    // e_a(q + c_a) - e_a(q - c_a), accS adds c^1_a x S_p to (W[0], W[1]) and
+    // c^2_a x S_p to (W[2], W[3]); flux projects them onto g^1 and g^2
+    __device__ __forceinline__ void accS(int a, T x, T (&W)[4]) const
+    {
+        const int c1 = cx(a), c2 = cy(a);
+        T sx, sy;
+        dS(a, sx, sy);
+        const T xs = sx * x, ys = sy * x;
+        if (c1 != 0) {
+            W[0] += (T)c1 * xs;
+            W[1] += (T)c1 * ys;
+        }
+        if (c2 != 0) {
+            W[2] += (T)c2 * xs;
+            W[3] += (T)c2 * ys;
+        }
+    }
+    __device__ __forceinline__ void flux(const T (&W)[4], T &P11, T &P12, T &P22) const
+    {
+        P11 = kpi * (W[0] * u1x + W[1] * u1y);
+        P22 = kpi * (W[2] * u2x + W[3] * u2y);
+        P12 = kpi * ((W[0] * u2x + W[1] * u2y) + (W[2] * u1x + W[3] * u1y));
+    }
+
     __device__ __forceinline__ T operator()(int f) const
     {
         if (f == TB::G11) return G11;
@@ -748,6 +789,41 @@ struct GeoTab {
         const T c1 = (T)cx(a), c2 = (T)cy(a);
         const T cGc = c1 * c1 * G11 + (T)2 * c1 * c2 * G12 + c2 * c2 * G22;
         return (T)(weight<Q>(a) / (2.0 * T0 * T0)) * (cGc - (T)T0 * (G11 + G22));
+    }
+
+    // direction sums formed on the vectors and projected once (as GeoTabF)
+    __device__ __forceinline__ void accA(int a, T x, T &V1, T &V2) const
+    {
+        double dx, dy;
+        dA(a, dx, dy);
+        V1 += (T)dx * x;
+        V2 += (T)dy * x;
+    }
+    __device__ __forceinline__ void proj(T V1, T V2, T &L1, T &L2) const
+    {
+        L1 += V1 * u1x + V2 * u1y;
+        L2 += V1 * u2x + V2 * u2y;
+    }
+    __device__ __forceinline__ void accS(int a, T x, T (&W)[4]) const
+    {
+        const int c1 = cx(a), c2 = cy(a);
+        double sx, sy;
+        dS(a, sx, sy);
+        const T xs = (T)sx * x, ys = (T)sy * x;
+        if (c1 != 0) {
+            W[0] += (T)c1 * xs;
+            W[1] += (T)c1 * ys;
+        }
+        if (c2 != 0) {
+            W[2] += (T)c2 * xs;
+            W[3] += (T)c2 * ys;
+        }
+    }
+    __device__ __forceinline__ void flux(const T (&W)[4], T &P11, T &P12, T &P22) const
+    {
+        P11 = kpi * (W[0] * u1x + W[1] * u1y);
+        P22 = kpi * (W[2] * u2x + W[3] * u2y);
+        P12 = kpi * ((W[0] * u2x + W[1] * u2y) + (W[2] * u1x + W[3] * u1y));
     }
 
     __device__ __forceinline__ T operator()(int f) const
@@ -999,12 +1075,24 @@ __device__ __forceinline__ void collide_cell(const InstDesc *__restrict__ d, con
     T JF1, JF2, Ut1, Ut2;
     // pulled part of the force sum: sum_a A+_a n_{-a} (pass independent)
     T Ln1 = tb(TB::C1), Ln2 = tb(TB::C2);
+    if constexpr (CT == 2) {
+        T V1 = 0, V2 = 0;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const int a = pair_rep(p), b = opp(a);
-        Ln1 += tb(TB::A1(a)) * n[b] + tb(TB::A1(b)) * n[a];
-        Ln2 += tb(TB::A2(a)) * n[b] + tb(TB::A2(b)) * n[a];
-        sgroup<CT>();
+        for (int p = 0; p < NP; ++p) {
+            const int a = pair_rep(p), b = opp(a);
+            tb.accA(a, n[b], V1, V2);
+            tb.accA(b, n[a], V1, V2);
+            sgroup<CT>();
+        }
+        tb.proj(V1, V2, Ln1, Ln2);
+    } else {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int a = pair_rep(p), b = opp(a);
+            Ln1 += tb(TB::A1(a)) * n[b] + tb(TB::A1(b)) * n[a];
+            Ln2 += tb(TB::A2(a)) * n[b] + tb(TB::A2(b)) * n[a];
+            sgroup<CT>();
+        }
     }
     phase_fence<CT>();
     for (int it = 0;; ++it) {
@@ -1013,6 +1101,14 @@ __device__ __forceinline__ void collide_cell(const InstDesc *__restrict__ d, con
         if (it == 0) {
             L1 += Lo1;
             L2 += Lo2;
+        } else if constexpr (CT == 2) {
+            T V1 = 0, V2 = 0;
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                tb.accA(a, s[a], V1, V2);
+                sgroup<CT>();
+            }
+            tb.proj(V1, V2, L1, L2);
         } else {
 #pragma unroll
             for (int a = 1; a < Q; ++a) {
@@ -1035,6 +1131,7 @@ __device__ __forceinline__ void collide_cell(const InstDesc *__restrict__ d, con
         const T uuT = (T)T0d * uu;
         T mO[NP], cUt[NP];
         T P11 = 0, P12 = 0, P22 = 0;
+        T W[4] = {0, 0, 0, 0};   // rebuilt fields: the flux sums' vectors
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int a = pair_rep(p);
@@ -1050,11 +1147,16 @@ __device__ __forceinline__ void collide_cell(const InstDesc *__restrict__ d, con
             const T mo = m * O;
             mO[p] = mo;
             cUt[p] = cut;
-            if (c1 != 0) P11 += tb(TB::X11(p)) * mo;
-            if (c2 != 0) P22 += tb(TB::X22(p)) * mo;
-            P12 += tb(TB::X12(p)) * mo;
+            if constexpr (CT == 2) {
+                tb.accS(a, mo, W);
+            } else {
+                if (c1 != 0) P11 += tb(TB::X11(p)) * mo;
+                if (c2 != 0) P22 += tb(TB::X22(p)) * mo;
+                P12 += tb(TB::X12(p)) * mo;
+            }
             sgroup<CT>();
         }
+        if constexpr (CT == 2) tb.flux(W, P11, P12, P22);
         const T trP = P11 + P22;
         phase_fence<CT>();
 
@@ -1172,27 +1274,21 @@ __device__ __forceinline__ void store_cell(const InstDesc *__restrict__ d, const
     const uint32_t rowb = WIDE ? 0u : (uint32_t)i * (uint32_t)d->sr * ES;
     const PScale<Q, S, T, CT == 0> ps;
     T Lx1 = 0, Lx2 = 0;
-    auto store_all = [&](auto with_sb) {
-#pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            const T sb = with_sb ? tb(TB::SB(a)) : (T)0;
-            const T st = s[a] + sb;                                             // storage base
-            pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + rowb, a, st);
-            if constexpr (LAGW) {
-                const T v = pdec<Q, S, T>(penc<Q, S, T>(st, a), a, ps) - sb;     // as stored, compute base
-                if (a > 0) {
-                    Lx1 += tb(TB::A1(a)) * v;
-                    Lx2 += tb(TB::A2(a)) * v;
-                }
-            }
-            sgroup<CT>();
-        }
-    };
     if constexpr (CT == 2) {
         // rebuilt fields: the storage base is the compute base (the local
         // rest state, or none in FP64), so the store needs no per-direction
-        // base terms
-        store_all(std::false_type{});
+        // base terms; the force sums are formed on the vectors
+        T V1 = 0, V2 = 0;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            pstore<Q, S, T>(rout, jb, (uint32_t)a * sa_b + rowb, a, s[a]);
+            if constexpr (LAGW) {
+                const T v = pdec<Q, S, T>(penc<Q, S, T>(s[a], a), a, ps);   // as stored
+                if (a > 0) tb.accA(a, v, V1, V2);
+            }
+            sgroup<CT>();
+        }
+        if constexpr (LAGW) tb.proj(V1, V2, Lx1, Lx2);
     } else {
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
