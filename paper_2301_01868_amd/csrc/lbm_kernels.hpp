@@ -166,22 +166,33 @@ __device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void *base, size_t row_b
     return make_rsrc((const char *)base + (long long)r0 * (long long)row_bytes, (uint32_t)(row_bytes * (size_t)nrows));
 }
 
-// Cache policy of the population and force-sum accesses: non-temporal (nt)
-// loads and stores (each value is touched once per step; measured faster
-// than the default policy on gfx950).
-#ifndef LBM_LD_AUX
-#define LBM_LD_AUX 2
-#endif
+// Cache policy of the population and force-sum accesses.  Stores are
+// non-temporal (nt): each value is written once per step.  Loads take the
+// policy measured fastest for the lattice and storage type on gfx950 (the
+// same kernels built both ways, alternating on one GPU): the pulled rows are
+// read again by the neighbouring rows' tiles, and with FP32 storage, and for
+// D2Q9 with FP64, the default policy keeps more of those re-reads in the
+// cache (D2Q21 FP32 group 300-302 against 309-312 us, one 4096 x 16384 FP32
+// grid 2049 against 2213 us, D2Q9 FP64 group about 310 against 349 us), while
+// D2Q21 with FP64 or FP16 storage, and the FP64 per-cell step, run faster with
+// nt loads (FP16 D2Q21 group 191-193 against 226-229 us).
 #ifndef LBM_ST_AUX
 #define LBM_ST_AUX 2
 #endif
-template <typename S, typename T>
+template <int Q, typename S>
+__host__ __device__ constexpr int ld_aux()
+{
+    if constexpr (sizeof(S) == 4) return 0;              // FP32: default
+    else if constexpr (sizeof(S) == 8) return Q == 9 ? 0 : 2;  // FP64: default for D2Q9, nt for D2Q21
+    else return 2;                                       // FP16: nt
+}
+template <typename S, typename T, int AUX>
 __device__ inline T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
     if constexpr (sizeof(S) == 8) {
-        return (T)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, LBM_LD_AUX));
+        return (T)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
     } else {
-        return (T)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LBM_LD_AUX));
+        return (T)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
     }
 }
 template <typename S, typename T>
@@ -236,10 +247,11 @@ __device__ inline T pload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff
                           const PScale<Q, S, T, VREG> &ps)
 {
     if constexpr (sizeof(S) == 2) {
-        const _Float16 h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LD_AUX));
+        const _Float16 h =
+            __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, ld_aux<Q, S>()));
         return (T)h * ps(a);
     } else {
-        return bload<S, T>(r, voff, soff);
+        return bload<S, T, ld_aux<Q, S>()>(r, voff, soff);
     }
 }
 template <int Q, typename S, typename T, bool VREG>
@@ -252,10 +264,11 @@ template <int Q, typename S, typename T>
 __device__ inline T pload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, int a)
 {
     if constexpr (sizeof(S) == 2) {
-        const _Float16 h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LD_AUX));
+        const _Float16 h =
+            __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, ld_aux<Q, S>()));
         return (T)h * (T)plane_scale<Q, S>(a);
     } else {
-        return bload<S, T>(r, voff, soff);
+        return bload<S, T, ld_aux<Q, S>()>(r, voff, soff);
     }
 }
 template <int Q, typename S, typename T>
@@ -1380,8 +1393,8 @@ __device__ __forceinline__ void step_tile(const InstDesc *__restrict__ insts, co
         const __amdgpu_buffer_rsrc_t rlag = WIDE ? row_rsrc(d->lag[pin], (size_t)d->lsr * ET, i, 1)
                                                  : make_rsrc(d->lag[pin], 2 * (uint32_t)d->plane * ET);
         const uint32_t jt = (uint32_t)j * ET, rowt = WIDE ? 0u : (uint32_t)i * (uint32_t)d->lsr * ET;
-        L1 = bload<T, T>(rlag, jt, rowt);
-        L2 = bload<T, T>(rlag, jt, lsa_b + rowt);
+        L1 = bload<T, T, ld_aux<Q, S>()>(rlag, jt, rowt);
+        L2 = bload<T, T, ld_aux<Q, S>()>(rlag, jt, lsa_b + rowt);
     };
 
     typename TabSel<Q, T, CT>::type tb;
